@@ -1,0 +1,155 @@
+/*
+ * hdmr.h -- C ABI of the MI355X (gfx950) library for anchored cut-HDMR
+ * expansions whose component functions are hierarchical sparse grids.
+ *
+ * Method: Eftekhari & Scheidegger, "High-Dimensional Dynamic Stochastic Model
+ * Representation" (arXiv 2202.06555).  A model represents
+ *
+ *     F(x) = c0 + sum_S w_S u_S(x_S),   u_S(x_S) = sum_j alpha_{S,j} prod_{q in S} phi_{l_jq,i_jq}(x_q)
+ *
+ * with the 1-D hat basis of eq (3.1), the odd index sets of eq (3.3) (zero
+ * boundary), the tensor basis of eq (3.2) and the interpolant of eq (3.6).
+ * With w_S = 1 and c0 = f(xbar) this is the cut-HDMR expansion of eq (3.16)
+ * grouped per component; with w_S = b_S of eq (4.2) it is the vectorised form
+ * a(x)^T b of Sec. 4.1.  Every alpha row carries m outputs (f : [0,1]^d -> R^m,
+ * Sec. 3.1).
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: HDMR_OK (0) or a negative HDMR_E* code; the message of the
+ *     last failure on the calling thread is available from hdmr_last_error().
+ *     No C++ exception crosses this boundary.
+ *   - Pointers named "host" are CPU memory; "dev" pointers are device memory
+ *     of the model's device (e.g. from hipMalloc or a torch CUDA tensor).  The
+ *     caller owns every buffer it passes and the library never frees them.
+ *     The library owns every hdmr_model until hdmr_free.
+ *   - Arrays are dense and row-major: points n x d, values n x m, gradients
+ *     n x d x m, all float64.  Device pointers must be 8-byte aligned.
+ *   - stream is a hipStream_t (NULL = the legacy default stream).  Evaluation
+ *     calls enqueue work on it and return without waiting; a fault inside a
+ *     kernel surfaces as HDMR_EDEVICE at the next call that synchronises.
+ *   - Points outside [0,1]^d evaluate with the zero extension eq (3.1) gives;
+ *     a NaN coordinate makes every output (and gradient entry) of that point NaN.
+ *   - Limits: |S| <= 4 per component, d <= 32767, 1 <= level <= 30, and
+ *     sum_q (l_q - 1) <= 31 for each stored level multi-index.
+ */
+#ifndef HDMR_H
+#define HDMR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HDMR_OK 0
+#define HDMR_EINVAL (-1)       /* bad argument: null pointer, shape, m mismatch, misalignment */
+#define HDMR_ENOMEM (-2)       /* host or device allocation failed                            */
+#define HDMR_EDEVICE (-3)      /* HIP runtime error (message has the HIP error string)        */
+#define HDMR_ECALLBACK (-4)    /* the user function returned non-zero                         */
+#define HDMR_EUNSUPPORTED (-5) /* outside the documented limits or not implemented            */
+
+#define HDMR_PLAIN_FP64 0      /* FP64 basis, FP64 contraction, FP64 sum                       */
+#define HDMR_MIXED 1           /* FP32 basis, split-BF16 MFMA contraction, FP64 anchor sum     */
+
+typedef struct hdmr_model hdmr_model;
+typedef void *hdmr_stream_t;   /* a hipStream_t */
+
+/* User function f : [0,1]^d -> R^m evaluated on the host: X is n x d (host),
+ * Y is n x m (host, written by f).  Returns 0 on success.  Must give identical
+ * outputs for identical rows. */
+typedef int (*hdmr_fn)(const double *X, int64_t n, int32_t d, double *Y, int32_t m, void *user);
+
+/* Library set-up on a device.  Optional: every entry point initialises the
+ * current device on first use.  Returns HDMR_EDEVICE if no device is usable. */
+int hdmr_init(int32_t device);
+
+/* ---------------------------------------------------------------------------
+ * Building a model from a function (Alg. 2 without the eta/rho criteria).
+ *
+ * For every index set S (explicit list, or all 1 <= |S| <= max_order), an
+ * adaptive sparse grid is grown by ascending level sums from the root
+ * (l = 1, i = 1).  Grid nodes get nodal values of the cut function
+ * g_S = f(xbar \ x_S) (Alg. 2 step 6) and of the cut-HDMR component
+ * u_S = sum_{v subset S} (-1)^{|S|-|v|} f(xbar \ x_v) (eq (2.2.6)); both are
+ * hierarchised on the device in FP64 (alpha = y - interpolant of the coarser
+ * level sums, the defining equations of eq (3.6)).  A node is accepted when
+ * max_o |alpha^g_o| > eps_gamma (eq (3.8)); the children of accepted nodes
+ * (l + e_q, 2 i_q -+ 1) are admitted when every parent (refine_rule 0) or any
+ * parent (refine_rule 1) is accepted (the exclusion rule of Sec. 3.1).
+ * eps_gamma < 0 accepts every node, which yields the regular grid of the
+ * level rule: eq (3.5) (level_rule 1: |l|_1 <= max_level + |S| - 1) or the
+ * full grid of eq (3.4) (level_rule 0: every l_q <= max_level).
+ * form 0 stores u_S with w_S = 1 and c0 = f(xbar); form 1 stores g_S with the
+ * eq (4.2) coefficients b_S and c0 = b_empty f(xbar).
+ * f is called on the host, once per level sum with every new node of every
+ * component (rows are deduplicated).  The result lives on the current device.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t d, m;                 /* input dimension, number of outputs                     */
+  int32_t max_order;            /* used when n_components == 0: all 1 <= |S| <= max_order */
+  int32_t max_level;            /* L                                                      */
+  int32_t level_rule;           /* 0: every l_q <= L;  1: |l|_1 <= L + |S| - 1            */
+  int32_t refine_rule;          /* 0: all parents accepted;  1: any parent accepted       */
+  double eps_gamma;             /* eq (3.8) threshold; < 0 = accept all                   */
+  const double *anchor;         /* host, d: the anchor point xbar (eq (2.2.5))            */
+  int32_t n_components;         /* 0 = all index sets up to max_order                     */
+  const int32_t *comp_offsets;  /* host, n_components+1 offsets into comp_dims            */
+  const int32_t *comp_dims;     /* host, the index sets, each strictly increasing         */
+  int32_t form;                 /* 0: component form; 1: eq (4.2) form                    */
+  double eps_eta, eps_rho;      /* eq (3.19)/(3.18) criteria: must be <= 0 here           */
+} asg_build_params;
+
+int asg_build_components(const asg_build_params *params, hdmr_fn f, void *user, hdmr_model **out);
+
+/* Model from given grids and surpluses (host arrays, copied to the current
+ * device).  Component s has index set comp_dims[comp_offsets[s] ..
+ * comp_offsets[s+1]) and comp_npts[s] rows; levels/indices hold
+ * sum_s comp_npts[s]*|S_s| entries (row-major per component, components
+ * concatenated), surpluses hold sum_s comp_npts[s]*m values, weights[s] is
+ * w_S, c0 has m values.  Levels must be >= 1, indices odd with
+ * 0 < i < 2^level (eq (3.3)), rows unique within a component. */
+int hdmr_model_from_surpluses(int32_t d, int32_t m, const double *c0, int32_t n_components,
+                              const int32_t *comp_offsets, const int32_t *comp_dims,
+                              const int64_t *comp_npts, const uint8_t *levels,
+                              const uint32_t *indices, const double *surpluses,
+                              const double *weights, hdmr_model **out);
+
+/* F at n points: points (dev, n x d), values (dev, n x m).  m must equal the
+ * model's m.  precision is HDMR_PLAIN_FP64 or HDMR_MIXED.  n = 0 is a no-op. */
+int hdmr_eval(const hdmr_model *model, const double *points, int64_t n, double *values, int32_t m,
+              int32_t precision, hdmr_stream_t stream);
+
+/* F and its gradient: grad (dev, n x d x m) receives dF_o/dx_q as the right
+ * partial derivative (the left one at x_q = 1; zero outside [0,1] and for
+ * dimensions no component uses).  values may be NULL. */
+int hdmr_eval_grad(const hdmr_model *model, const double *points, int64_t n, double *values,
+                   double *grad, int32_t m, hdmr_stream_t stream);
+
+/* Sizes of a model (host). */
+typedef struct {
+  int32_t d, m, n_components, n_tuples;
+  int64_t n_rows;               /* stored grid points over all components          */
+  int64_t device_bytes;         /* device memory the model holds                   */
+  int32_t max_level;            /* largest level in any dimension                   */
+  int32_t max_k;                /* largest |S|                                      */
+} hdmr_model_info;
+
+int hdmr_get_info(const hdmr_model *model, hdmr_model_info *info);
+
+/* Copy one component's grid back to the host, in the model's internal row
+ * order: *npts rows, *k = |S|, dims (k entries, host), levels/indices
+ * (npts x k, host), surpluses (npts x m, host), *weight = w_S.  Every output
+ * pointer except npts may be NULL; query npts and k first, then allocate. */
+int hdmr_export_component(const hdmr_model *model, int32_t comp, int64_t *npts, int32_t *k, int32_t *dims,
+                          uint8_t *levels, uint32_t *indices, double *surpluses, double *weight);
+
+void hdmr_free(hdmr_model *model);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *hdmr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HDMR_H */

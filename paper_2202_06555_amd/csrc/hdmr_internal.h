@@ -1,0 +1,127 @@
+// Internal declarations shared by the host and device sources of libhdmr.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hdmr.h"
+
+namespace hdmr {
+
+constexpr int KMAX = 4;        // largest |S| a component may have
+constexpr int MAX_LEVEL = 30;  // largest level per dimension
+
+// How the row of the active cell of a level multi-index is found.
+enum TupKind : uint8_t {
+  TUP_FULL = 0,   // every cell stored: row = row_base + slot
+  TUP_DENSE = 1,  // int32 slot table at tab[aux .. aux + ncells): row or -1
+  TUP_HASH = 2,   // open addressing at tab[aux .. aux + 2*(mask+1)): (slot, row) pairs
+};
+
+// One stored level multi-index l of one component ("tuple").  Its rows are
+// contiguous and sorted by slot, the mixed-radix number of the cell
+// (c_q = (i_q - 1) / 2 per dimension, last dimension fastest).
+struct alignas(16) TupDesc {
+  double w;          // weight w_S of the owning component
+  int32_t row_base;  // first row of the tuple
+  int32_t aux;       // table offset (DENSE, HASH)
+  int32_t mask;      // hash capacity - 1 (HASH)
+  int32_t comp;      // owning component
+  int16_t dims[KMAX];
+  uint8_t lv[KMAX];
+  uint8_t k, kind, lsum, pad_;
+};
+static_assert(sizeof(TupDesc) == 48, "TupDesc layout");
+
+// Device view of a model (passed to kernels by value).
+struct ModelView {
+  const TupDesc *tups;
+  const int32_t *tab;
+  const double *alpha;   // n_rows x m, FP64
+  const double *c0;      // m
+  const int32_t *comp_tup;  // n_components + 1: tuple ranges per component
+  int32_t ntup, ncomp, d, m;
+};
+
+struct Component {
+  int32_t k;
+  int32_t dims[KMAX];
+  double w;
+  int64_t row_begin, row_end;    // global rows
+  int32_t tup_begin, tup_end;    // global tuples
+};
+
+}  // namespace hdmr
+
+struct hdmr_model {
+  int device = 0;
+  int32_t d = 0, m = 0;
+  int64_t n_rows = 0;
+  int32_t max_level = 0, max_k = 0;
+  std::vector<hdmr::Component> comps;
+  std::vector<hdmr::TupDesc> tups_h;
+  // host copies in internal row order (export, rebuilds)
+  std::vector<uint8_t> lv_h;     // n_rows x KMAX
+  std::vector<uint32_t> ix_h;    // n_rows x KMAX
+  std::vector<double> c0_h;
+  // device buffers (owned)
+  hdmr::TupDesc *tups = nullptr;
+  int32_t *tab = nullptr;
+  double *alpha = nullptr;
+  double *c0 = nullptr;
+  int32_t *comp_tup = nullptr;
+  int64_t tab_entries = 0;
+  int64_t device_bytes = 0;
+
+  hdmr::ModelView view() const {
+    return hdmr::ModelView{tups, tab, alpha, c0, comp_tup, (int32_t)tups_h.size(), (int32_t)comps.size(), d, m};
+  }
+};
+
+namespace hdmr {
+
+// thread-local error message + status helpers
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+void clear_error();
+
+#define HDMR_HIP(call)                                   \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hdmr::hip_fail(e_, #call); \
+  } while (0)
+
+// Construct the device model from host rows (defined in model.hip).
+struct HostComponent {
+  int32_t k;
+  int32_t dims[KMAX];
+  double w;
+  int64_t n;
+  const uint8_t *lv;    // n x k
+  const uint32_t *ix;   // n x k
+  const double *alpha;  // n x m
+};
+int make_model(int32_t d, int32_t m, const double *c0, const std::vector<HostComponent> &comps, hdmr_model **out);
+
+int set_device_of(const hdmr_model *model);
+
+}  // namespace hdmr
+
+namespace hdmr {
+
+// Slot hash of HASH tuples (integer finaliser; host and device agree).
+__host__ __device__ inline uint32_t slot_hash(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352dU;
+  x ^= x >> 15;
+  x *= 0x846ca68bU;
+  x ^= x >> 16;
+  return x;
+}
+
+constexpr uint32_t HASH_EMPTY = 0xFFFFFFFFu;
+
+}  // namespace hdmr

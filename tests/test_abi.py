@@ -1,0 +1,52 @@
+"""The C-ABI library loads and exports every function include/hdmr.h declares;
+host-side argument checks (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "hdmr.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:int|void|const char \*)\s*\**\s*(\w+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_header_symbols():
+    import paper_2202_06555_amd as hd
+    L = hd.lib()
+    names = _header_functions()
+    assert len(names) >= 9
+    for nm in names:
+        assert hasattr(L, nm), nm
+    assert sorted(hd.EXPORTS) == names
+
+
+def test_host_validation_errors():
+    import paper_2202_06555_amd as hd
+    import workloads.synth as ws
+    good = ws.synthetic_regular_model(d=3, m=2, order=1, ell=2, seed=0)
+    bad = dict(good)
+    bad["indices"] = [ix.copy() for ix in good["indices"]]
+    bad["indices"][0][0, 0] = 2            # even index violates eq (3.3)
+    with pytest.raises(hd.HdmrError) as e:
+        hd.hdmr_model_from_surpluses(bad)
+    assert e.value.code == hd.hdmr.HDMR_EINVAL
+    dup = dict(good)
+    dup["levels"] = [np.vstack([lv, lv[:1]]) for lv in good["levels"]]
+    dup["indices"] = [np.vstack([ix, ix[:1]]) for ix in good["indices"]]
+    dup["alpha"] = [np.vstack([a, a[:1]]) for a in good["alpha"]]
+    with pytest.raises(hd.HdmrError) as e:
+        hd.hdmr_model_from_surpluses(dup)
+    assert "duplicate" in str(e.value)
+    big = dict(good)
+    big["comps"] = [(0, 1, 2, 0, 1)] + list(good["comps"][1:])
+    with pytest.raises(hd.HdmrError) as e:
+        hd.hdmr_model_from_surpluses(big)
+    assert e.value.code == hd.hdmr.HDMR_EUNSUPPORTED
+    assert hd.hdmr_last_error() != ""
