@@ -125,6 +125,14 @@ int hdmr_eval(const hdmr_model *model, const double *points, int64_t n, double *
 int hdmr_eval_grad(const hdmr_model *model, const double *points, int64_t n, double *values,
                    double *grad, int32_t m, hdmr_stream_t stream);
 
+/* Work counts of an evaluation (diagnostic, synchronous on stream): *hits
+ * receives the number of (point, stored row) pairs with a nonzero basis
+ * product -- the nonzeros of the sparse basis matrix of eq (3.6) summed over
+ * components -- and *probes the number of (point, level multi-index) lookups
+ * the kernels perform.  Used to price a launch in flops (2 * hits * m). */
+int hdmr_eval_stats(const hdmr_model *model, const double *points, int64_t n, int64_t *hits, int64_t *probes,
+                    hdmr_stream_t stream);
+
 /* Sizes of a model (host). */
 typedef struct {
   int32_t d, m, n_components, n_tuples;

@@ -1,0 +1,605 @@
+// asg_build_components: adaptive cut-HDMR build (Alg. 2 without the eta/rho
+// criteria) with FP64 hierarchisation on the device.
+//
+// All components advance together by level sum s.  Per step:
+//   host   : the new nodes of every component (root first, then admitted
+//            children), the rows x = xbar \ x_v they need (deduplicated over
+//            nodes, components and steps), one call of f, and per node the cut
+//            value g_S = f(xbar \ x_S) and the component value
+//            u_S = sum_v (-1)^{|S|-|v|} f(xbar \ x_v) (eq (2.2.6)) taken as
+//            nested differences over the dimensions of S;
+//   device : k_hierarchize_fp64 -- alpha = y - (interpolant of the rows of
+//            smaller level sum at the node), for g and u together (2m
+//            columns), and the eq (3.8) test max_o |alpha^g_o| > eps_gamma;
+//   host   : the new level multi-indices join the lookup directory and the
+//            children (l + e_q, 2 i_q -+ 1) of accepted nodes are admitted by
+//            the parent rule (Sec. 3.1 exclusion).
+// At the end the surpluses of u_S (form 0) or of g_S with the eq (4.2)
+// weights (form 1) are gathered into a regular model.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+
+#include "kernels_common.h"
+
+namespace hdmr {
+
+namespace {
+
+struct NodeDev {
+  int32_t comp;
+  int32_t row;      // build row receiving the surpluses
+  uint8_t lv[KMAX];
+  uint32_t ix[KMAX];
+};
+
+// One wave per new node: evaluate the component's existing interpolant (all
+// rows of smaller level sum) at the node, subtract from the nodal values.
+template <int OPL>
+__global__ __launch_bounds__(256) void k_hierarchize_fp64(const TupDesc *__restrict__ tups,
+                                                          const int32_t *__restrict__ tab, double *__restrict__ alpha,
+                                                          int32_t M2, int32_t m, const int32_t *__restrict__ ct_off,
+                                                          const int32_t *__restrict__ ct_ids,
+                                                          const NodeDev *__restrict__ nodes, int64_t nnodes,
+                                                          const double *__restrict__ y, double eps,
+                                                          uint8_t *__restrict__ accepted) {
+  __shared__ int32_t qrow_s[WAVES_PER_BLOCK][WAVE];
+  __shared__ double qw_s[WAVES_PER_BLOCK][WAVE];
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wid = threadIdx.x / WAVE;
+  int32_t *qrow = qrow_s[wid];
+  double *qw = qw_s[wid];
+  const int64_t wave_id = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wid;
+  const int64_t nwaves = (int64_t)gridDim.x * WAVES_PER_BLOCK;
+  for (int64_t j = wave_id; j < nnodes; j += nwaves) {
+    const NodeDev nd = nodes[j];
+    double xs[KMAX];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) xs[q] = (double)nd.ix[q] / (double)(1u << (nd.lv[q] ? nd.lv[q] : 1));
+    double acc[OPL];
+#pragma unroll
+    for (int u = 0; u < OPL; ++u) acc[u] = 0.0;
+    const int tb = ct_off[nd.comp], te = ct_off[nd.comp + 1];
+    for (int t0 = tb; t0 < te; t0 += WAVE) {
+      const int t = t0 + lane;
+      int32_t row = -1;
+      double w = 0.0;
+      if (t < te) {
+        const TupDesc T = tups[ct_ids[t]];
+        w = 1.0;
+        uint32_t slot = 0;
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q) {
+          if (q < T.k) {
+            uint32_t half, c;
+            double phi, tt;
+            active_cell(xs[q], T.lv[q], half, phi, tt, c);
+            w *= phi;
+            slot = (slot << (T.lv[q] - 1)) | half;
+          }
+        }
+        if (w != 0.0) row = lookup_row(T, slot, tab);
+      }
+      const bool hit = row >= 0;
+      const uint64_t mask = ballot(hit);
+      const int cnt = __popcll(mask);
+      if (hit) {
+        const int pos = lanes_below(mask);
+        qrow[pos] = row;
+        qw[pos] = w;
+      }
+      wave_sync();
+      for (int h = 0; h < cnt; ++h) {
+        const int32_t r = qrow[h];
+        const double ww = qw[h];
+#pragma unroll
+        for (int u = 0; u < OPL; ++u) {
+          const int o = lane + u * WAVE;
+          if (o < M2) acc[u] = fma(ww, alpha[(int64_t)r * M2 + o], acc[u]);
+        }
+      }
+      wave_sync();
+    }
+    double gmax = 0.0;
+    bool gnan = false;
+#pragma unroll
+    for (int u = 0; u < OPL; ++u) {
+      const int o = lane + u * WAVE;
+      if (o < M2) {
+        const double a = y[j * M2 + o] - acc[u];
+        alpha[(int64_t)nd.row * M2 + o] = a;
+        if (o < m) {
+          gmax = fmax(gmax, fabs(a));
+          gnan |= (a != a);
+        }
+      }
+    }
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) gmax = fmax(gmax, __shfl_xor(gmax, off, WAVE));
+    gnan = ballot(gnan) != 0;
+    if (lane == 0) accepted[j] = (eps < 0.0) ? 1 : ((!gnan && gmax > eps) ? 1 : 0);
+  }
+}
+
+struct NodeKey {
+  std::array<uint8_t, KMAX> l;
+  std::array<uint32_t, KMAX> i;
+  bool operator==(const NodeKey &o) const { return l == o.l && i == o.i; }
+};
+struct NodeKeyHash {
+  size_t operator()(const NodeKey &k) const {
+    uint64_t h = 1469598103934665603ULL;
+    for (int q = 0; q < KMAX; ++q) {
+      h ^= (uint64_t)k.l[q] * 0x9E3779B97F4A7C15ULL + k.i[q];
+      h *= 1099511628211ULL;
+      h ^= h >> 31;
+    }
+    return (size_t)h;
+  }
+};
+
+// Key of a row xbar \ x_v: the (dimension, value) pairs that differ from xbar.
+struct RowKey {
+  int32_t n;
+  std::array<int32_t, KMAX> dim;
+  std::array<uint64_t, KMAX> bits;
+  bool operator==(const RowKey &o) const {
+    if (n != o.n) return false;
+    for (int q = 0; q < n; ++q)
+      if (dim[q] != o.dim[q] || bits[q] != o.bits[q]) return false;
+    return true;
+  }
+};
+struct RowKeyHash {
+  size_t operator()(const RowKey &k) const {
+    uint64_t h = 0x12345678ULL + (uint64_t)k.n;
+    for (int q = 0; q < k.n; ++q) {
+      h ^= (uint64_t)k.dim[q] * 0x9E3779B97F4A7C15ULL;
+      h *= 1099511628211ULL;
+      h ^= k.bits[q] + (h << 6) + (h >> 2);
+    }
+    return (size_t)h;
+  }
+};
+
+struct CompState {
+  int32_t k;
+  int32_t dims[KMAX];
+  std::unordered_map<NodeKey, int32_t, NodeKeyHash> index;  // node -> local row
+  std::vector<uint8_t> acc;                                   // per local row
+  std::vector<uint8_t> lv;                                    // local rows x k
+  std::vector<uint32_t> ix;
+  std::vector<int64_t> build_row;                             // local row -> build row
+  std::vector<int32_t> tuples;                                // build tuple ids
+  std::vector<NodeKey> pending;                               // nodes of the next step
+};
+
+template <typename T>
+int grow_device(T **ptr, int64_t *cap, int64_t need, int64_t used) {
+  if (need <= *cap) return HDMR_OK;
+  int64_t nc = std::max<int64_t>(*cap * 2, 1024);
+  while (nc < need) nc *= 2;
+  T *np = nullptr;
+  HDMR_HIP(hipMalloc((void **)&np, (size_t)nc * sizeof(T)));
+  if (*ptr && used > 0) HDMR_HIP(hipMemcpy(np, *ptr, (size_t)used * sizeof(T), hipMemcpyDeviceToDevice));
+  if (*ptr) HDMR_HIP(hipFree(*ptr));
+  *ptr = np;
+  *cap = nc;
+  return HDMR_OK;
+}
+
+inline uint64_t dbits(double v) {
+  uint64_t b;
+  std::memcpy(&b, &v, 8);
+  return b;
+}
+
+struct DeviceBuffers {
+  TupDesc *tups = nullptr;
+  int32_t *tab = nullptr;
+  double *alpha = nullptr;
+  int64_t tups_cap = 0, tab_cap = 0, alpha_cap = 0;
+  ~DeviceBuffers() {
+    (void)hipFree(tups);
+    (void)hipFree(tab);
+    (void)hipFree(alpha);
+  }
+};
+
+}  // namespace
+
+}  // namespace hdmr
+
+using namespace hdmr;
+
+extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *user, hdmr_model **out) {
+  clear_error();
+  if (!P || !f || !out || !P->anchor) return fail(HDMR_EINVAL, "asg_build_components: null argument");
+  *out = nullptr;
+  const int d = P->d, m = P->m, M2 = 2 * m;
+  if (d < 1 || d > 32767 || m < 1 || m > 256) return fail(HDMR_EINVAL, "d must be in [1,32767] and m in [1,256]");
+  if (P->max_level < 1 || P->max_level > MAX_LEVEL) return fail(HDMR_EINVAL, "max_level must be in [1,30]");
+  if (P->level_rule != 0 && P->level_rule != 1) return fail(HDMR_EINVAL, "level_rule must be 0 or 1");
+  if (P->refine_rule != 0 && P->refine_rule != 1) return fail(HDMR_EINVAL, "refine_rule must be 0 or 1");
+  if (P->form != 0 && P->form != 1) return fail(HDMR_EINVAL, "form must be 0 or 1");
+  if (P->eps_eta > 0.0 || P->eps_rho > 0.0)
+    return fail(HDMR_EUNSUPPORTED, "the eta/rho expansion criteria are not implemented (pass values <= 0)");
+  // ---- component list ----
+  std::vector<CompState> C;
+  if (P->n_components > 0) {
+    if (!P->comp_offsets || !P->comp_dims) return fail(HDMR_EINVAL, "null component list");
+    for (int s = 0; s < P->n_components; ++s) {
+      CompState c;
+      c.k = P->comp_offsets[s + 1] - P->comp_offsets[s];
+      if (c.k < 1 || c.k > KMAX) return fail(HDMR_EUNSUPPORTED, "component sizes must be in [1,4]");
+      for (int q = 0; q < c.k; ++q) {
+        c.dims[q] = P->comp_dims[P->comp_offsets[s] + q];
+        if (c.dims[q] < 0 || c.dims[q] >= d || (q && c.dims[q] <= c.dims[q - 1]))
+          return fail(HDMR_EINVAL, "component dimensions must be strictly increasing and < d");
+      }
+      C.push_back(std::move(c));
+    }
+  } else {
+    if (P->max_order < 1 || P->max_order > KMAX) return fail(HDMR_EUNSUPPORTED, "max_order must be in [1,4]");
+    for (int k = 1; k <= P->max_order; ++k) {
+      std::array<int32_t, KMAX> v{};
+      for (int q = 0; q < k; ++q) v[q] = q;
+      if (k > d) break;
+      for (;;) {
+        CompState c;
+        c.k = k;
+        for (int q = 0; q < k; ++q) c.dims[q] = v[q];
+        C.push_back(std::move(c));
+        int q = k - 1;
+        while (q >= 0 && v[q] == d - k + q) --q;
+        if (q < 0) break;
+        ++v[q];
+        for (int r = q + 1; r < k; ++r) v[r] = v[r - 1] + 1;
+      }
+    }
+  }
+  const int ncomp = (int)C.size();
+  std::vector<double> anchor(P->anchor, P->anchor + d);
+  for (auto &c : C) {
+    NodeKey root{};
+    for (int q = 0; q < c.k; ++q) {
+      root.l[q] = 1;
+      root.i[q] = 1;
+    }
+    c.pending.push_back(root);
+  }
+  // ---- row cache for f(xbar \ x_v) with |v| < |S| ----
+  std::unordered_map<RowKey, int64_t, RowKeyHash> cache;
+  std::vector<double> cache_val;
+  DeviceBuffers D;
+  std::vector<TupDesc> h_tups;
+  int64_t tab_used = 0, rows_used = 0;
+  int32_t lsum_top = P->level_rule == 1 ? P->max_level + KMAX - 1 : P->max_level * KMAX;
+  for (int32_t step = 1; step <= lsum_top; ++step) {
+    // ---- collect this step's nodes ----
+    struct NewNode {
+      int32_t comp;
+      NodeKey key;
+      uint32_t lvkey, slot;
+    };
+    std::vector<NewNode> nn;
+    for (int s = 0; s < ncomp; ++s) {
+      CompState &c = C[s];
+      if (c.pending.empty()) continue;
+      int32_t ls0 = 0;
+      for (int q = 0; q < c.k; ++q) ls0 += c.pending[0].l[q];
+      if (ls0 != step) continue;
+      for (const NodeKey &key : c.pending) {
+        uint32_t lk = 0, sl = 0;
+        for (int q = 0; q < c.k; ++q) {
+          lk = (lk << 8) | key.l[q];
+          sl = (sl << (key.l[q] - 1)) | ((key.i[q] - 1) >> 1);
+        }
+        nn.push_back(NewNode{s, key, lk, sl});
+      }
+      c.pending.clear();
+    }
+    if (nn.empty()) {
+      bool any = false;
+      for (auto &c : C) any |= !c.pending.empty();
+      if (!any) break;
+      continue;
+    }
+    std::stable_sort(nn.begin(), nn.end(), [](const NewNode &a, const NewNode &b) {
+      if (a.comp != b.comp) return a.comp < b.comp;
+      if (a.lvkey != b.lvkey) return a.lvkey < b.lvkey;
+      return a.slot < b.slot;
+    });
+    const int64_t N = (int64_t)nn.size();
+    // ---- rows to evaluate ----
+    std::vector<int64_t> ref((size_t)N << KMAX, -1);   // per node and subset: cache row or -(fresh+2)
+    std::vector<RowKey> fresh_keys;
+    std::vector<RowKey> new_cache_keys;
+    for (int64_t j = 0; j < N; ++j) {
+      const CompState &c = C[nn[j].comp];
+      double xs[KMAX];
+      for (int q = 0; q < c.k; ++q) xs[q] = std::ldexp((double)nn[j].key.i[q], -(int)nn[j].key.l[q]);
+      const int nsub = 1 << c.k;
+      for (int v = 0; v < nsub; ++v) {
+        RowKey rk{};
+        for (int q = 0; q < c.k; ++q)
+          if ((v >> q) & 1)
+            if (!(xs[q] == anchor[c.dims[q]])) {
+              rk.dim[rk.n] = c.dims[q];
+              rk.bits[rk.n] = dbits(xs[q]);
+              ++rk.n;
+            }
+        if (v == nsub - 1 && rk.n == c.k) {
+          ref[(size_t)(j << KMAX) + v] = -(int64_t)fresh_keys.size() - 2;
+          fresh_keys.push_back(rk);
+          continue;
+        }
+        auto it = cache.find(rk);
+        if (it == cache.end()) {
+          int64_t id = (int64_t)(cache_val.size() / m) + (int64_t)new_cache_keys.size();
+          it = cache.emplace(rk, id).first;
+          new_cache_keys.push_back(rk);
+        }
+        ref[(size_t)(j << KMAX) + v] = it->second;
+      }
+    }
+    // ---- one call of f for every new row ----
+    const int64_t nfresh = (int64_t)fresh_keys.size(), ncache_new = (int64_t)new_cache_keys.size();
+    const int64_t nrows_f = nfresh + ncache_new;
+    std::vector<double> X((size_t)nrows_f * d), Y((size_t)nrows_f * m);
+    for (int64_t r = 0; r < nrows_f; ++r) {
+      const RowKey &rk = r < ncache_new ? new_cache_keys[r] : fresh_keys[r - ncache_new];
+      double *row = &X[(size_t)r * d];
+      std::memcpy(row, anchor.data(), sizeof(double) * d);
+      for (int q = 0; q < rk.n; ++q) std::memcpy(&row[rk.dim[q]], &rk.bits[q], 8);
+    }
+    if (nrows_f > 0 && f(X.data(), nrows_f, d, Y.data(), m, user) != 0)
+      return fail(HDMR_ECALLBACK, "the user function returned an error");
+    cache_val.insert(cache_val.end(), Y.begin(), Y.begin() + (size_t)ncache_new * m);
+    // ---- nodal values: g = f(xbar \ x_S), u = nested differences ----
+    std::vector<double> yv((size_t)N * M2);
+    std::vector<double> buf((size_t)m << KMAX);
+    for (int64_t j = 0; j < N; ++j) {
+      const CompState &c = C[nn[j].comp];
+      const int nsub = 1 << c.k;
+      for (int v = 0; v < nsub; ++v) {
+        const int64_t r = ref[(size_t)(j << KMAX) + v];
+        const double *src = r >= 0 ? &cache_val[(size_t)r * m] : &Y[(size_t)(ncache_new + (-r - 2)) * m];
+        std::memcpy(&buf[(size_t)v * m], src, sizeof(double) * m);
+      }
+      for (int o = 0; o < m; ++o) yv[(size_t)j * M2 + o] = buf[(size_t)(nsub - 1) * m + o];
+      for (int q = 0; q < c.k; ++q)
+        for (int v = 0; v < nsub; ++v)
+          if ((v >> q) & 1)
+            for (int o = 0; o < m; ++o) buf[(size_t)v * m + o] -= buf[(size_t)(v ^ (1 << q)) * m + o];
+      for (int o = 0; o < m; ++o) yv[(size_t)j * M2 + m + o] = buf[(size_t)(nsub - 1) * m + o];
+    }
+    // ---- device: hierarchise against the existing directory ----
+    std::vector<NodeDev> nd((size_t)N);
+    for (int64_t j = 0; j < N; ++j) {
+      nd[j].comp = nn[j].comp;
+      nd[j].row = (int32_t)(rows_used + j);
+      for (int q = 0; q < KMAX; ++q) {
+        nd[j].lv[q] = nn[j].key.l[q];
+        nd[j].ix[q] = nn[j].key.i[q];
+      }
+    }
+    std::vector<int32_t> ct_off((size_t)ncomp + 1, 0), ct_ids;
+    for (int s = 0; s < ncomp; ++s) {
+      ct_off[s] = (int32_t)ct_ids.size();
+      ct_ids.insert(ct_ids.end(), C[s].tuples.begin(), C[s].tuples.end());
+    }
+    ct_off[ncomp] = (int32_t)ct_ids.size();
+    if (rows_used + N >= (int64_t)INT32_MAX) return fail(HDMR_EUNSUPPORTED, "more than 2^31-1 grid points");
+    int rc = grow_device(&D.alpha, &D.alpha_cap, (rows_used + N) * M2, rows_used * M2);
+    if (rc) return rc;
+    NodeDev *d_nodes = nullptr;
+    double *d_y = nullptr;
+    int32_t *d_ctoff = nullptr, *d_ctids = nullptr;
+    uint8_t *d_acc = nullptr;
+    std::vector<uint8_t> acc((size_t)N);
+    auto cleanup = [&]() {
+      (void)hipFree(d_nodes);
+      (void)hipFree(d_y);
+      (void)hipFree(d_ctoff);
+      (void)hipFree(d_ctids);
+      (void)hipFree(d_acc);
+    };
+    hipError_t e = hipSuccess;
+    if ((e = hipMalloc((void **)&d_nodes, sizeof(NodeDev) * N)) != hipSuccess ||
+        (e = hipMalloc((void **)&d_y, sizeof(double) * N * M2)) != hipSuccess ||
+        (e = hipMalloc((void **)&d_ctoff, sizeof(int32_t) * (ncomp + 1))) != hipSuccess ||
+        (e = hipMalloc((void **)&d_ctids, sizeof(int32_t) * std::max<size_t>(ct_ids.size(), 1))) != hipSuccess ||
+        (e = hipMalloc((void **)&d_acc, N)) != hipSuccess ||
+        (e = hipMemcpy(d_nodes, nd.data(), sizeof(NodeDev) * N, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d_y, yv.data(), sizeof(double) * N * M2, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d_ctoff, ct_off.data(), sizeof(int32_t) * (ncomp + 1), hipMemcpyHostToDevice)) != hipSuccess ||
+        (ct_ids.size() &&
+         (e = hipMemcpy(d_ctids, ct_ids.data(), sizeof(int32_t) * ct_ids.size(), hipMemcpyHostToDevice)) !=
+             hipSuccess)) {
+      cleanup();
+      return hip_fail(e, "build step upload");
+    }
+    {
+      dim3 grid((unsigned)std::min<int64_t>((N + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, 65535)), block(256);
+      const int opl = (M2 + WAVE - 1) / WAVE;
+#define HIER(OPLV)                                                                                             \
+  hipLaunchKernelGGL(k_hierarchize_fp64<OPLV>, grid, block, 0, (hipStream_t)0, D.tups, D.tab, D.alpha, M2, m, \
+                     d_ctoff, d_ctids, d_nodes, N, d_y, P->eps_gamma, d_acc)
+      if (opl <= 1) HIER(1);
+      else if (opl <= 2) HIER(2);
+      else if (opl <= 4) HIER(4);
+      else HIER(8);
+#undef HIER
+      e = hipGetLastError();
+      if (e == hipSuccess) e = hipMemcpy(acc.data(), d_acc, N, hipMemcpyDeviceToHost);
+    }
+    cleanup();
+    if (e != hipSuccess) return hip_fail(e, "k_hierarchize_fp64");
+    // ---- register the new rows; append their level multi-indices ----
+    std::vector<int32_t> tab_new;
+    int64_t t0 = 0;
+    while (t0 < N) {
+      int64_t t1 = t0;
+      while (t1 < N && nn[t1].comp == nn[t0].comp && nn[t1].lvkey == nn[t0].lvkey) ++t1;
+      CompState &c = C[nn[t0].comp];
+      TupDesc T{};
+      T.w = 1.0;
+      T.row_base = (int32_t)(rows_used + t0);
+      T.comp = nn[t0].comp;
+      T.k = (uint8_t)c.k;
+      T.lsum = (uint8_t)step;
+      int64_t ncells = 1;
+      for (int q = 0; q < c.k; ++q) {
+        T.dims[q] = (int16_t)c.dims[q];
+        T.lv[q] = nn[t0].key.l[q];
+        ncells <<= (T.lv[q] - 1);
+      }
+      const int64_t nr = t1 - t0;
+      const int64_t base = tab_used + (int64_t)tab_new.size();
+      if (nr == ncells) {
+        T.kind = TUP_FULL;
+      } else if (ncells <= 4 * nr + 64) {
+        T.kind = TUP_DENSE;
+        T.aux = (int32_t)base;
+        tab_new.resize(tab_new.size() + (size_t)ncells, -1);
+        for (int64_t t = t0; t < t1; ++t) tab_new[(size_t)(base - tab_used) + nn[t].slot] = (int32_t)(rows_used + t);
+      } else {
+        T.kind = TUP_HASH;
+        int64_t cap = 4;
+        while (cap < 2 * nr) cap <<= 1;
+        int64_t b2 = base;
+        if (b2 & 1) {
+          tab_new.push_back(0);
+          ++b2;
+        }
+        T.aux = (int32_t)b2;
+        T.mask = (int32_t)(cap - 1);
+        const size_t off = (size_t)(b2 - tab_used);
+        tab_new.resize(off + 2 * (size_t)cap, 0);
+        for (int64_t q = 0; q < cap; ++q) tab_new[off + 2 * q] = (int32_t)HASH_EMPTY;
+        for (int64_t t = t0; t < t1; ++t) {
+          uint32_t h = slot_hash(nn[t].slot) & (uint32_t)T.mask;
+          while ((uint32_t)tab_new[off + 2 * h] != HASH_EMPTY) h = (h + 1) & (uint32_t)T.mask;
+          tab_new[off + 2 * h] = (int32_t)nn[t].slot;
+          tab_new[off + 2 * h + 1] = (int32_t)(rows_used + t);
+        }
+      }
+      c.tuples.push_back((int32_t)h_tups.size());
+      h_tups.push_back(T);
+      for (int64_t t = t0; t < t1; ++t) {
+        const int32_t local = (int32_t)c.acc.size();
+        c.index.emplace(nn[t].key, local);
+        c.acc.push_back(acc[t]);
+        for (int q = 0; q < c.k; ++q) {
+          c.lv.push_back(nn[t].key.l[q]);
+          c.ix.push_back(nn[t].key.i[q]);
+        }
+        c.build_row.push_back(rows_used + t);
+      }
+      t0 = t1;
+    }
+    if (tab_used + (int64_t)tab_new.size() >= (int64_t)INT32_MAX)
+      return fail(HDMR_EUNSUPPORTED, "lookup directory exceeds 2^31 entries");
+    if ((rc = grow_device(&D.tab, &D.tab_cap, tab_used + (int64_t)tab_new.size(), tab_used))) return rc;
+    if (!tab_new.empty())
+      HDMR_HIP(hipMemcpy(D.tab + tab_used, tab_new.data(), sizeof(int32_t) * tab_new.size(), hipMemcpyHostToDevice));
+    tab_used += (int64_t)tab_new.size();
+    const int64_t tups_before = D.tups ? (int64_t)h_tups.size() : 0;
+    (void)tups_before;
+    if ((rc = grow_device(&D.tups, &D.tups_cap, (int64_t)h_tups.size(), 0))) return rc;
+    HDMR_HIP(hipMemcpy(D.tups, h_tups.data(), sizeof(TupDesc) * h_tups.size(), hipMemcpyHostToDevice));
+    rows_used += N;
+    // ---- children of accepted nodes (Sec. 3.1 exclusion rule) ----
+    for (int64_t j = 0; j < N; ++j) {
+      if (!acc[j]) continue;
+      CompState &c = C[nn[j].comp];
+      const NodeKey &key = nn[j].key;
+      int32_t ls = 0;
+      for (int q = 0; q < c.k; ++q) ls += key.l[q];
+      if (P->level_rule == 1 && ls + 1 > P->max_level + c.k - 1) continue;
+      for (int q = 0; q < c.k; ++q) {
+        if (P->level_rule == 0 && key.l[q] + 1 > P->max_level) continue;
+        for (int side = -1; side <= 1; side += 2) {
+          NodeKey ch = key;
+          ch.l[q] = (uint8_t)(ch.l[q] + 1);
+          ch.i[q] = 2 * ch.i[q] + side;
+          int npar = 0, nacc = 0;
+          for (int p = 0; p < c.k; ++p) {
+            if (ch.l[p] <= 1) continue;
+            NodeKey par = ch;
+            par.l[p] = (uint8_t)(par.l[p] - 1);
+            const uint32_t a = (ch.i[p] - 1) / 2, b = (ch.i[p] + 1) / 2;
+            par.i[p] = (a & 1u) ? a : b;
+            ++npar;
+            auto it = c.index.find(par);
+            if (it != c.index.end() && c.acc[it->second]) ++nacc;
+          }
+          const bool admit = P->refine_rule == 0 ? (nacc == npar) : (nacc > 0);
+          if (admit) c.pending.push_back(ch);
+        }
+      }
+    }
+    for (auto &c : C) {
+      if (c.pending.size() < 2) continue;
+      std::sort(c.pending.begin(), c.pending.end(), [&](const NodeKey &a, const NodeKey &b) {
+        for (int q = 0; q < c.k; ++q)
+          if (a.l[q] != b.l[q]) return a.l[q] < b.l[q];
+        for (int q = 0; q < c.k; ++q)
+          if (a.i[q] != b.i[q]) return a.i[q] < b.i[q];
+        return false;
+      });
+      c.pending.erase(std::unique(c.pending.begin(), c.pending.end()), c.pending.end());
+    }
+  }
+  // ---- assemble the model ----
+  std::vector<double> f_anchor((size_t)m);
+  {
+    RowKey rk{};
+    auto it = cache.find(rk);
+    if (it != cache.end()) {
+      std::memcpy(f_anchor.data(), &cache_val[(size_t)it->second * m], sizeof(double) * m);
+    } else if (f(anchor.data(), 1, d, f_anchor.data(), m, user) != 0) {
+      return fail(HDMR_ECALLBACK, "the user function returned an error");
+    }
+  }
+  std::vector<double> weights((size_t)ncomp, 1.0);
+  std::vector<double> c0 = f_anchor;
+  if (P->form == 1) {
+    // eq (4.2): b_i = sum over retained u containing i of (-1)^{|u|-|i|}; the
+    // retained family is the component list plus the empty set.
+    auto contains = [&](const CompState &u, const CompState &i) {
+      for (int q = 0; q < i.k; ++q) {
+        bool found = false;
+        for (int r = 0; r < u.k; ++r) found |= (u.dims[r] == i.dims[q]);
+        if (!found) return false;
+      }
+      return true;
+    };
+    int64_t b_empty = 1;
+    for (int u = 0; u < ncomp; ++u) b_empty += (C[u].k % 2) ? -1 : 1;
+    for (int s = 0; s < ncomp; ++s) {
+      int64_t b = 0;
+      for (int u = 0; u < ncomp; ++u)
+        if (contains(C[u], C[s])) b += ((C[u].k - C[s].k) % 2) ? -1 : 1;
+      weights[s] = (double)b;
+    }
+    for (int o = 0; o < m; ++o) c0[o] = (double)b_empty * f_anchor[o];
+  }
+  std::vector<HostComponent> hc((size_t)ncomp);
+  for (int s = 0; s < ncomp; ++s) {
+    HostComponent &h = hc[s];
+    h.k = C[s].k;
+    for (int q = 0; q < KMAX; ++q) h.dims[q] = C[s].dims[q];
+    h.w = weights[s];
+    h.n = (int64_t)C[s].acc.size();
+    h.lv = C[s].lv.data();
+    h.ix = C[s].ix.data();
+    h.alpha = nullptr;
+    h.src_rows = C[s].build_row.data();
+  }
+  DeviceAlphaSource src{D.alpha, M2, P->form == 0 ? m : 0};
+  return make_model(d, m, c0.data(), hc, out, &src);
+}

@@ -13,61 +13,14 @@
 //             is small) and accumulate w * alpha[row, o] in FP64 registers,
 //             coalesced along the m-contiguous surplus row (eq (3.6));
 //   store   : lane groups are reduced and c0 + sum is written (eq (3.16)).
-#include "hdmr_internal.h"
+#include <cstdlib>
+#include <cstring>
+
+#include "kernels_common.h"
 
 namespace hdmr {
 
 namespace {
-
-constexpr int WAVE = 64;
-constexpr int WAVES_PER_BLOCK = 4;
-
-// Active cell of level l at coordinate x: c = min(floor(x 2^l), 2^l - 1)
-// (clamped to the domain), odd index i = c | 1, t = x 2^l - i (exact),
-// phi = max(0, 1 - |t|) is eq (3.1).  Outside [0,1] phi is 0.
-__device__ __forceinline__ void active_cell(double x, int l, uint32_t &half, double &phi, double &t,
-                                            uint32_t &c) {
-  double scale = (double)(1u << l);
-  double xl = x * scale;
-  double cf = fmin(fmax(floor(xl), 0.0), scale - 1.0);
-  c = (uint32_t)cf;
-  t = xl - (double)(c | 1u);
-  phi = fmax(0.0, 1.0 - fabs(t));
-  half = c >> 1;
-}
-
-__device__ __forceinline__ int32_t lookup_row(const TupDesc &T, uint32_t slot, const int32_t *__restrict__ tab) {
-  if (T.kind == TUP_FULL) return T.row_base + (int32_t)slot;
-  if (T.kind == TUP_DENSE) return tab[T.aux + (int64_t)slot];
-  const int2 *ht = reinterpret_cast<const int2 *>(tab + T.aux);
-  uint32_t h = slot_hash(slot) & (uint32_t)T.mask;
-  for (;;) {
-    int2 e = ht[h];
-    if ((uint32_t)e.x == slot) return e.y;
-    if ((uint32_t)e.x == HASH_EMPTY) return -1;
-    h = (h + 1) & (uint32_t)T.mask;
-  }
-}
-
-__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
-
-// Make LDS writes of one lane visible to the other lanes of the same wave.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ int lanes_below(uint64_t mask) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
-}
-
-template <int OW>
-__device__ __forceinline__ double reduce_groups(double v) {
-#pragma unroll
-  for (int off = OW; off < WAVE; off <<= 1) v += __shfl_xor(v, off, WAVE);
-  return v;
-}
 
 struct WaveLds {
   double *xs;     // d coordinates
@@ -163,7 +116,7 @@ __global__ __launch_bounds__(256) void k_eval_fp64(ModelView M, const double *__
           if (o < m) {
             double a[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) a[u] = M.alpha[(int64_t)r[u] * m + o];
+            for (int u = 0; u < 4; ++u) a[u] = M.alpha[(int64_t)r[u] * M.ms + o];
 #pragma unroll
             for (int u = 0; u < 4; ++u) acc[j] = fma(ww[u], a[u], acc[j]);
           }
@@ -175,7 +128,7 @@ __global__ __launch_bounds__(256) void k_eval_fp64(ModelView M, const double *__
 #pragma unroll
         for (int j = 0; j < OPL; ++j) {
           const int o = ol + j * WAVE;
-          if (o < m) acc[j] = fma(ww, M.alpha[(int64_t)r * m + o], acc[j]);
+          if (o < m) acc[j] = fma(ww, M.alpha[(int64_t)r * M.ms + o], acc[j]);
         }
       }
       wave_sync();
@@ -289,7 +242,7 @@ __global__ __launch_bounds__(256) void k_eval_grad_fp64(ModelView M, const doubl
           for (int j = 0; j < OPL; ++j) {
             const int o = ol + j * WAVE;
             if (o < m) {
-              const double a = M.alpha[(int64_t)r * m + o];
+              const double a = M.alpha[(int64_t)r * M.ms + o];
               acc[j] = fma(ww, a, acc[j]);
 #pragma unroll
               for (int q = 0; q < KMAX; ++q)
@@ -328,6 +281,42 @@ __global__ __launch_bounds__(256) void k_eval_grad_fp64(ModelView M, const doubl
   }
 }
 
+// Lookup phase only: counts hits (nonzero basis products) and probes.
+__global__ __launch_bounds__(256) void k_count_hits(ModelView M, const double *__restrict__ X, int64_t n,
+                                                    unsigned long long *__restrict__ counters) {
+  extern __shared__ __align__(16) char smem[];
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wid = threadIdx.x / WAVE;
+  const int d = M.d;
+  double *xs = reinterpret_cast<double *>(smem) + (size_t)wid * d;
+  const int64_t wave_id = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wid;
+  const int64_t nwaves = (int64_t)gridDim.x * WAVES_PER_BLOCK;
+  unsigned long long hits = 0, probes = 0;
+  for (int64_t p = wave_id; p < n; p += nwaves) {
+    stage_point(X, p, d, xs, lane);
+    for (int t = lane; t < M.ntup; t += WAVE) {
+      const TupDesc T = M.tups[t];
+      double w = T.w;
+      uint32_t slot = 0;
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q) {
+        if (q < T.k) {
+          uint32_t half, c;
+          double phi, tt;
+          active_cell(xs[T.dims[q]], T.lv[q], half, phi, tt, c);
+          w *= phi;
+          slot = (slot << (T.lv[q] - 1)) | half;
+        }
+      }
+      ++probes;
+      if (w != 0.0 && lookup_row(T, slot, M.tab) >= 0) ++hits;
+    }
+    wave_sync();
+  }
+  atomicAdd(&counters[0], hits);
+  atomicAdd(&counters[1], probes);
+}
+
 __global__ void k_fill(double *__restrict__ a, int64_t n, double v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) a[i] = v;
 }
@@ -351,6 +340,17 @@ int grid_for(int64_t n) {
     else hipLaunchKernelGGL((KERNEL<64, 4>), grid_, block_, SMEM, stream, __VA_ARGS__);      \
   } while (0)
 
+// Large batches go through the cell-sorted kernels; small ones (and models
+// without grid points) through the single-launch gather kernel.  The
+// environment variable HDMR_EVAL_PATH=gather|sorted overrides the choice.
+bool use_sorted_path(const hdmr_model *model, int64_t n) {
+  if (model->passes.empty()) return false;
+  const char *env = std::getenv("HDMR_EVAL_PATH");
+  if (env && std::strcmp(env, "gather") == 0) return false;
+  if (env && std::strcmp(env, "sorted") == 0) return true;
+  return n >= 16384;
+}
+
 int check_eval_args(const hdmr_model *model, const double *points, int64_t n, const double *values, int32_t m,
                     bool values_required) {
   if (!model) return fail(HDMR_EINVAL, "null model");
@@ -371,8 +371,8 @@ using namespace hdmr;
 
 extern "C" {
 
-int hdmr_eval_mixed_impl(const hdmr_model *model, const double *points, int64_t n, double *values,
-                         hipStream_t stream);
+__attribute__((visibility("hidden"))) int hdmr_eval_mixed_impl(const hdmr_model *model, const double *points,
+                                                             int64_t n, double *values, hipStream_t stream);
 
 int hdmr_eval(const hdmr_model *model, const double *points, int64_t n, double *values, int32_t m,
               int32_t precision, hdmr_stream_t stream_) {
@@ -384,12 +384,43 @@ int hdmr_eval(const hdmr_model *model, const double *points, int64_t n, double *
   if ((rc = set_device_of(model))) return rc;
   hipStream_t stream = (hipStream_t)stream_;
   if (precision == HDMR_MIXED) return hdmr_eval_mixed_impl(model, points, n, values, stream);
+  if (use_sorted_path(model, n)) return eval_sorted_fp64(model, points, n, values, stream);
   const ModelView M = model->view();
   const size_t per = ((size_t)M.d * 8 + 64 * 8 + 64 * 4 + 15) & ~(size_t)15;
   const size_t smem = per * WAVES_PER_BLOCK;
   if (smem > 65536) return fail(HDMR_EUNSUPPORTED, "d too large for the LDS staging of points");
   EVAL_DISPATCH(k_eval_fp64, smem, M, points, n, values);
   HDMR_HIP(hipGetLastError());
+  return HDMR_OK;
+}
+
+int hdmr_eval_stats(const hdmr_model *model, const double *points, int64_t n, int64_t *hits, int64_t *probes,
+                    hdmr_stream_t stream_) {
+  clear_error();
+  int rc = check_eval_args(model, points, n, nullptr, model ? model->m : 0, false);
+  if (rc) return rc;
+  if (!hits || !probes) return fail(HDMR_EINVAL, "null output");
+  *hits = 0;
+  *probes = 0;
+  if (n == 0) return HDMR_OK;
+  if ((rc = set_device_of(model))) return rc;
+  hipStream_t stream = (hipStream_t)stream_;
+  const ModelView M = model->view();
+  const size_t smem = (size_t)M.d * 8 * WAVES_PER_BLOCK;
+  if (smem > 65536) return fail(HDMR_EUNSUPPORTED, "d too large for the LDS staging of points");
+  unsigned long long *dc = nullptr, hc[2] = {0, 0};
+  HDMR_HIP(hipMalloc((void **)&dc, sizeof(hc)));
+  hipError_t e = hipMemsetAsync(dc, 0, sizeof(hc), stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_count_hits, dim3(grid_for(n)), dim3(WAVE * WAVES_PER_BLOCK), smem, stream, M, points, n, dc);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(hc, dc, sizeof(hc), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  (void)hipFree(dc);
+  if (e != hipSuccess) return hip_fail(e, "k_count_hits");
+  *hits = (int64_t)hc[0];
+  *probes = (int64_t)hc[1];
   return HDMR_OK;
 }
 

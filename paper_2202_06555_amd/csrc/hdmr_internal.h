@@ -40,10 +40,28 @@ static_assert(sizeof(TupDesc) == 48, "TupDesc layout");
 struct ModelView {
   const TupDesc *tups;
   const int32_t *tab;
-  const double *alpha;   // n_rows x m, FP64
+  const double *alpha;   // n_rows x ms, FP64 (row stride ms = m rounded up to even)
   const double *c0;      // m
   const int32_t *comp_tup;  // n_components + 1: tuple ranges per component
-  int32_t ntup, ncomp, d, m;
+  int32_t ntup, ncomp, d, m, ms;
+};
+
+// One sorted evaluation pass: points are ordered by their cell in the key
+// dimensions (cell_lv[q] levels of dims[q]); the listed components (whose
+// dimensions are a subset of the key) are evaluated together.
+constexpr int PASS_MAX_COMPS = 8;
+struct Pass {
+  int32_t k;
+  int32_t dims[KMAX];
+  int32_t cell_lv[KMAX];
+  int32_t shift[KMAX];
+  int32_t key_bits;
+  int32_t tup_begin, tup_end;  // range in the pass-tuple list
+};
+// A tuple as seen from a pass: key position of each of its dimensions.
+struct alignas(8) PassTup {
+  int32_t tup;
+  uint8_t pos[KMAX];
 };
 
 struct Component {
@@ -58,7 +76,7 @@ struct Component {
 
 struct hdmr_model {
   int device = 0;
-  int32_t d = 0, m = 0;
+  int32_t d = 0, m = 0, ms = 0;
   int64_t n_rows = 0;
   int32_t max_level = 0, max_k = 0;
   std::vector<hdmr::Component> comps;
@@ -75,9 +93,14 @@ struct hdmr_model {
   int32_t *comp_tup = nullptr;
   int64_t tab_entries = 0;
   int64_t device_bytes = 0;
+  // sorted-evaluation plan
+  std::vector<hdmr::Pass> passes;
+  std::vector<hdmr::PassTup> pass_tups_h;
+  hdmr::PassTup *pass_tups = nullptr;
+  int32_t max_pass_tups = 0;
 
   hdmr::ModelView view() const {
-    return hdmr::ModelView{tups, tab, alpha, c0, comp_tup, (int32_t)tups_h.size(), (int32_t)comps.size(), d, m};
+    return hdmr::ModelView{tups, tab, alpha, c0, comp_tup, (int32_t)tups_h.size(), (int32_t)comps.size(), d, m, ms};
   }
 };
 
@@ -102,11 +125,25 @@ struct HostComponent {
   int64_t n;
   const uint8_t *lv;    // n x k
   const uint32_t *ix;   // n x k
-  const double *alpha;  // n x m
+  const double *alpha;  // n x m (host), or NULL when src_rows is given
+  const int64_t *src_rows;  // n rows of a device source matrix (see DeviceAlphaSource)
 };
-int make_model(int32_t d, int32_t m, const double *c0, const std::vector<HostComponent> &comps, hdmr_model **out);
+// Surpluses already on the device: row r of component c is
+// src[c.src_rows[r] * stride + col .. + m).
+struct DeviceAlphaSource {
+  const double *src;
+  int32_t stride, col;
+};
+int make_model(int32_t d, int32_t m, const double *c0, const std::vector<HostComponent> &comps, hdmr_model **out,
+               const DeviceAlphaSource *dsrc = nullptr);
 
 int set_device_of(const hdmr_model *model);
+
+// Cell-sorted FP64 evaluation (eval_sorted.hip).
+int eval_sorted_fp64(const hdmr_model *model, const double *X, int64_t n, double *F, hipStream_t stream);
+
+// Plan the sorted-evaluation passes of a model and upload the pass tuples.
+int plan_passes(hdmr_model *M);
 
 }  // namespace hdmr
 

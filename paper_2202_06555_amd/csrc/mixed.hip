@@ -4,7 +4,7 @@
 
 using namespace hdmr;
 
-extern "C" int hdmr_eval_mixed_impl(const hdmr_model *model, const double *points, int64_t n, double *values,
+extern "C" __attribute__((visibility("hidden"))) int hdmr_eval_mixed_impl(const hdmr_model *model, const double *points, int64_t n, double *values,
                                     hipStream_t stream) {
   (void)model; (void)points; (void)n; (void)values; (void)stream;
   return fail(HDMR_EUNSUPPORTED, "mixed precision path not built yet");

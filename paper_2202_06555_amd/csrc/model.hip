@@ -54,6 +54,8 @@ void free_device(hdmr_model *M) {
   (void)hipFree(M->alpha);
   (void)hipFree(M->c0);
   (void)hipFree(M->comp_tup);
+  (void)hipFree(M->pass_tups);
+  M->pass_tups = nullptr;
   M->tups = nullptr;
   M->tab = nullptr;
   M->alpha = nullptr;
@@ -63,13 +65,26 @@ void free_device(hdmr_model *M) {
 
 }  // namespace
 
-int make_model(int32_t d, int32_t m, const double *c0, const std::vector<HostComponent> &hc, hdmr_model **out) {
+__global__ void k_gather_rows(double *__restrict__ dst, const double *__restrict__ src, const int64_t *__restrict__ map,
+                              int64_t nrows, int32_t m, int32_t ms, int32_t stride, int32_t col) {
+  const int64_t total = nrows * ms;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / ms;
+    const int32_t o = (int32_t)(e - r * ms);
+    dst[e] = o < m ? src[map[r] * stride + col + o] : 0.0;
+  }
+}
+
+int make_model(int32_t d, int32_t m, const double *c0, const std::vector<HostComponent> &hc, hdmr_model **out,
+               const DeviceAlphaSource *dsrc) {
   if (d < 1 || d > 32767) return fail(HDMR_EINVAL, "d must be in [1, 32767]");
   if (m < 1) return fail(HDMR_EINVAL, "m must be >= 1");
   auto M = new (std::nothrow) hdmr_model();
   if (!M) return fail(HDMR_ENOMEM, "host allocation failed");
   M->d = d;
   M->m = m;
+  M->ms = (m + 1) & ~1;
+  const int32_t ms = M->ms;
   M->c0_h.assign(c0, c0 + m);
   int64_t total = 0;
   for (auto &c : hc) total += c.n;
@@ -79,7 +94,8 @@ int make_model(int32_t d, int32_t m, const double *c0, const std::vector<HostCom
   }
   M->lv_h.assign((size_t)total * KMAX, 0);
   M->ix_h.assign((size_t)total * KMAX, 0);
-  std::vector<double> alpha_sorted((size_t)total * m);
+  std::vector<double> alpha_sorted(dsrc ? 0 : (size_t)total * ms, 0.0);
+  std::vector<int64_t> gather(dsrc ? (size_t)total : 0);
   std::vector<int32_t> tab;
   std::vector<int32_t> comp_tup;
   int64_t row0 = 0;
@@ -151,7 +167,10 @@ int make_model(int32_t d, int32_t m, const double *c0, const std::vector<HostCom
         M->ix_h[r * KMAX + q] = c.ix[j * c.k + q];
         M->max_level = std::max<int32_t>(M->max_level, c.lv[j * c.k + q]);
       }
-      std::memcpy(&alpha_sorted[(size_t)r * m], c.alpha + j * m, sizeof(double) * m);
+      if (dsrc)
+        gather[(size_t)r] = c.src_rows[j];
+      else
+        std::memcpy(&alpha_sorted[(size_t)r * ms], c.alpha + j * m, sizeof(double) * m);
     }
     // one directory entry per stored level multi-index
     int64_t t0 = 0;
@@ -217,15 +236,119 @@ int make_model(int32_t d, int32_t m, const double *c0, const std::vector<HostCom
   }
   if ((rc = dev_upload(&M->tups, M->tups_h.data(), M->tups_h.size(), &M->device_bytes)) ||
       (rc = dev_upload(&M->tab, tab.data(), tab.size(), &M->device_bytes)) ||
-      (rc = dev_upload(&M->alpha, alpha_sorted.data(), alpha_sorted.size(), &M->device_bytes)) ||
+      (rc = dsrc ? HDMR_OK : dev_upload(&M->alpha, alpha_sorted.data(), alpha_sorted.size(), &M->device_bytes)) ||
       (rc = dev_upload(&M->c0, M->c0_h.data(), M->c0_h.size(), &M->device_bytes)) ||
       (rc = dev_upload(&M->comp_tup, comp_tup.data(), comp_tup.size(), &M->device_bytes))) {
     free_device(M);
     delete M;
     return rc;
   }
+  if (dsrc) {
+    int64_t *dmap = nullptr;
+    int64_t scratch = 0;
+    hipError_t e = hipMalloc((void **)&M->alpha, std::max<size_t>((size_t)total * ms, 1) * sizeof(double));
+    if (e == hipSuccess) {
+      M->device_bytes += std::max<int64_t>(total * ms, 1) * (int64_t)sizeof(double);
+      rc = dev_upload(&dmap, gather.data(), gather.size(), &scratch);
+      if (rc == HDMR_OK && total > 0) {
+        hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)std::min<int64_t>((total * ms + 255) / 256, 65536)),
+                           dim3(256), 0, (hipStream_t)0, M->alpha, dsrc->src, dmap, total, m, ms, dsrc->stride,
+                           dsrc->col);
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) rc = hip_fail(e, "gather surpluses");
+      }
+      (void)hipFree(dmap);
+    } else {
+      rc = hip_fail(e, "hipMalloc(alpha)");
+    }
+    if (rc) {
+      free_device(M);
+      delete M;
+      return rc;
+    }
+  }
+  if ((rc = plan_passes(M))) {
+    free_device(M);
+    delete M;
+    return rc;
+  }
   *out = M;
   return HDMR_OK;
+}
+
+int plan_passes(hdmr_model *M) {
+  // one pass per component of the largest order; lower-order components ride
+  // along with the first pass whose key holds their dimensions
+  M->passes.clear();
+  M->pass_tups_h.clear();
+  const int nc = (int)M->comps.size();
+  std::vector<int> order(nc);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return M->comps[a].k > M->comps[b].k; });
+  std::vector<int> owner(nc, -1);
+  std::vector<std::vector<int>> members;
+  for (int s : order) {
+    const Component &c = M->comps[s];
+    if (c.tup_begin == c.tup_end) continue;
+    int found = -1;
+    for (size_t p = 0; p < M->passes.size() && found < 0; ++p) {
+      const Pass &P = M->passes[p];
+      if ((int)members[p].size() >= PASS_MAX_COMPS) continue;
+      bool sub = true;
+      for (int q = 0; q < c.k && sub; ++q) {
+        bool in = false;
+        for (int r = 0; r < P.k; ++r) in |= (P.dims[r] == c.dims[q]);
+        sub = in;
+      }
+      if (sub) found = (int)p;
+    }
+    if (found < 0) {
+      Pass P{};
+      P.k = c.k;
+      for (int q = 0; q < c.k; ++q) P.dims[q] = c.dims[q];
+      M->passes.push_back(P);
+      members.emplace_back();
+      found = (int)M->passes.size() - 1;
+    }
+    members[found].push_back(s);
+    owner[s] = found;
+  }
+  for (size_t p = 0; p < M->passes.size(); ++p) {
+    Pass &P = M->passes[p];
+    int lmax[KMAX] = {0, 0, 0, 0};
+    P.tup_begin = (int32_t)M->pass_tups_h.size();
+    for (int s : members[p]) {
+      const Component &c = M->comps[s];
+      for (int t = c.tup_begin; t < c.tup_end; ++t) {
+        const TupDesc &T = M->tups_h[t];
+        PassTup pt{};
+        pt.tup = t;
+        for (int q = 0; q < T.k; ++q) {
+          int pos = 0;
+          while (P.dims[pos] != T.dims[q]) ++pos;
+          pt.pos[q] = (uint8_t)pos;
+          lmax[pos] = std::max<int>(lmax[pos], T.lv[q]);
+        }
+        M->pass_tups_h.push_back(pt);
+      }
+    }
+    P.tup_end = (int32_t)M->pass_tups_h.size();
+    M->max_pass_tups = std::max(M->max_pass_tups, P.tup_end - P.tup_begin);
+    // cells of a pass: the finest stored level per key dimension, within a
+    // 16-bit key
+    const int cap = 16 / P.k;
+    int shift = 0;
+    for (int q = P.k - 1; q >= 0; --q) {
+      P.cell_lv[q] = std::max(1, std::min(lmax[q], cap));
+      P.shift[q] = shift;
+      shift += P.cell_lv[q];
+    }
+    P.key_bits = shift;
+  }
+  int64_t scratch = 0;
+  (void)hipFree(M->pass_tups);
+  M->pass_tups = nullptr;
+  return dev_upload(&M->pass_tups, M->pass_tups_h.data(), M->pass_tups_h.size(), &scratch);
 }
 
 }  // namespace hdmr
@@ -308,8 +431,8 @@ int hdmr_export_component(const hdmr_model *model, int32_t comp, int64_t *npts, 
   if (surpluses && n) {
     int rc = set_device_of(model);
     if (rc) return rc;
-    HDMR_HIP(hipMemcpy(surpluses, model->alpha + c.row_begin * model->m, sizeof(double) * n * model->m,
-                       hipMemcpyDeviceToHost));
+    HDMR_HIP(hipMemcpy2D(surpluses, sizeof(double) * model->m, model->alpha + c.row_begin * model->ms,
+                         sizeof(double) * model->ms, sizeof(double) * model->m, (size_t)n, hipMemcpyDeviceToHost));
   }
   return HDMR_OK;
 }

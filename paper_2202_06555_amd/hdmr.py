@@ -29,7 +29,7 @@ MIXED = 1
 # every function the header declares (checked by the tests)
 EXPORTS = (
     "hdmr_init", "asg_build_components", "hdmr_model_from_surpluses", "hdmr_eval", "hdmr_eval_grad",
-    "hdmr_get_info", "hdmr_export_component", "hdmr_free", "hdmr_last_error",
+    "hdmr_get_info", "hdmr_export_component", "hdmr_free", "hdmr_last_error", "hdmr_eval_stats",
 )
 
 _LOCK = threading.Lock()
@@ -76,6 +76,7 @@ def lib():
                 "hdmr_eval": [vp, vp, i64, vp, i32, i32, vp],
                 "hdmr_eval_grad": [vp, vp, i64, vp, vp, i32, vp],
                 "hdmr_get_info": [vp, vp],
+                "hdmr_eval_stats": [vp, vp, i64, vp, vp, vp],
                 "hdmr_export_component": [vp, i32, vp, vp, vp, vp, vp, vp, vp],
             }
             for name, args in sig.items():
@@ -229,6 +230,16 @@ def hdmr_eval_grad(model: Model, points, values=None, grad=None, stream=None):
     _check(lib().hdmr_eval_grad(model.handle, _dev(points, "points", (n, d)), n, _dev(values, "values", (n, m)),
                                 _dev(grad, "grad", (n, d, m)), m, _stream_ptr(stream)))
     return values, grad
+
+
+def hdmr_eval_stats(model: Model, points, stream=None):
+    """(hits, probes): nonzero basis products and directory lookups of an evaluation."""
+    inf = hdmr_get_info(model)
+    n = points.shape[0]
+    h, p = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().hdmr_eval_stats(model.handle, _dev(points, "points", (n, inf["d"])), n, ctypes.byref(h),
+                                 ctypes.byref(p), _stream_ptr(stream)))
+    return h.value, p.value
 
 
 def hdmr_get_info(model: Model):
