@@ -1,30 +1,64 @@
 """Benchmark of the hot path: batched evaluation of an anchored cut-HDMR
-expansion with adaptive sparse-grid components (the metric workload: d=100,
+expansion with adaptive sparse-grid components.  Default workload: d=100,
 100 one-dimensional + 500 two-dimensional components, adaptive grids to level
-8 with eps_gamma = 1e-4, m = 51 outputs, 4e6 next-state points).
+8 with eps_gamma = 1e-4, m = 51 outputs, 4e6 next-state points.
 
 One step = one hdmr_eval over all points, inputs resident in HBM.  Prints one
-JSON line (see the keys below).  The model is built on the device with
-asg_build_components from the seeded synthetic test function (untimed).
+JSON line.  The model is built on the device with asg_build_components from
+the seeded synthetic test function (untimed).  The device time of every
+evaluation stage is taken live with device events on the launch stream
+(hdmr_timing_*); the roofline object prices the dominant stage, the
+matrix-core contraction, by its algorithmic work:
+  flops : 2 per (point, stored row with a nonzero basis product, output);
+  bytes : 8 per (point, output) for the first pass's write, 16 per (point,
+          output) for every later pass's read-modify-write, 8 per stored
+          surplus (FP64; 4 for the mixed path's FP32 copy), 8 per (point,
+          key dimension) of sorted coordinates and 4 per (point, pass) of
+          sorted point ids.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision plain|mixed]
-                  [--no-cpu-baseline] [--points N]
+                  [--no-cpu-baseline] [--points N] [--calibrate-copy]
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP64_PEAK = 78.6e12     # MI355X FP64 vector FLOP/s (public spec)
-HBM_PEAK = 8.0e12       # MI355X HBM3E bytes/s (public spec)
+FP64_PEAK = 78.6e12      # MI355X FP64 matrix / vector FLOP/s
+BF16_PEAK = 2.5e15       # MI355X dense BF16 matrix FLOP/s
+HBM_PEAK = 8.0e12        # MI355X HBM3E bytes/s
+
+KERNEL = {"plain": "k_tile_fp64", "mixed": "k_tile_mixed<3>"}
 
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def _source_hash():
+    with open(os.path.join(ROOT, "paper_2202_06555_amd", "csrc", "eval_sorted.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _measured_traffic(kernel, workload):
+    """HBM bytes per launch of the contraction kernel from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when
+    there is none or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.md" % (kernel.split("<")[0], workload))
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    h = re.search(r"source_sha256:\s*([0-9a-f]{64})", txt)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not h or not b or h.group(1) != _source_hash():
+        return None
+    return float(b.group(1))
 
 
 def main():
@@ -36,14 +70,15 @@ def main():
     ap.add_argument("--points", type=int, default=None)
     ap.add_argument("--config", default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2000)
+    ap.add_argument("--cpu-sample", type=int, default=20000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 1 GiB device copy first (scale reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the evaluation shards by points with no exchange, "
-              "so --gpus N > 1 is not run in this build", file=sys.stderr)
+              "so --gpus N > 1 is not run here", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2202_06555_amd as hd
@@ -54,13 +89,21 @@ def main():
     hd.hdmr_init(0)
     cfg = ws.config(args.config)
     n = cfg["n"] if args.points is None else args.points
+    if args.calibrate_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("calibration copy: 1 GiB read + 1 GiB written")
     tf = ws.test_function_for(cfg)
     t0 = time.time()
     model = hd.asg_build_components(cfg["d"], cfg["m"], cfg["anchor"], (tf.c_fn, tf.c_user), comps=cfg["comps"],
                                     max_level=cfg["max_level"], eps_gamma=cfg["eps_gamma"])
     info = hd.hdmr_get_info(model)
-    log("built model on device in %.1f s: %d components, %d rows, %.2f GB" %
-        (time.time() - t0, info["n_components"], info["n_rows"], info["device_bytes"] / 1e9))
+    log("built model on device in %.1f s: %d components, %d rows, %d passes, %.2f GB" %
+        (time.time() - t0, info["n_components"], info["n_rows"], info["n_passes"], info["device_bytes"] / 1e9))
     X = torch.from_numpy(ws.points_for(cfg, n=n)).to(dev)
     m, d = cfg["m"], cfg["d"]
     Y = torch.empty((n, m), dtype=torch.float64, device=dev)
@@ -72,22 +115,61 @@ def main():
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    hd.hdmr_timing_enable(True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
-        hd.hdmr_eval(model, X, Y, precision=prec)
+        hd.hdmr_eval(model, X, Y, precision=prec, stream=stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
+    stages = {s: hd.hdmr_timing_read(s) for s in ("sort", "rows", "contract")}
+    hd.hdmr_timing_enable(False)
     ms = ev0.elapsed_time(ev1) / args.steps
     t = ms / 1e3
     value = n * m / t
-    flops = 2.0 * hits * m + n * m           # FMA per (nonzero, output) + anchor add
-    achieved = flops / t
+    log("step %.2f ms; per step: sort %.1f ms, rows %.1f ms, contract %.1f ms" %
+        (ms, stages["sort"][0] / args.steps, stages["rows"][0] / args.steps, stages["contract"][0] / args.steps))
+
+    # roofline of the contraction kernel (one launch per pass and 64-output chunk)
+    c_ms, c_launches = stages["contract"]
+    launches_per_step = c_launches / args.steps
+    per_launch_s = c_ms / 1e3 / c_launches
+    P = info["n_passes"]
+    surplus_bytes = 8 if prec == hd.PLAIN_FP64 else 4
+    flops_step = 2.0 * hits * m
+    bytes_step = (n * m * 8.0 * (2 * P - 1) + info["n_rows"] * m * surplus_bytes +
+                  n * (8.0 * info["pass_key_dims"] + 4.0 * P))
+    flops_launch = flops_step / launches_per_step
+    bytes_launch = bytes_step / launches_per_step
+    mfma_peak = FP64_PEAK if prec == hd.PLAIN_FP64 else BF16_PEAK
+    f_frac = flops_launch / per_launch_s / mfma_peak
+    b_frac = bytes_launch / per_launch_s / HBM_PEAK
+    kern = KERNEL[args.precision]
+    traffic = _measured_traffic(kern, args.config)
+    if b_frac >= f_frac:
+        roof = {"bound": "hbm", "achieved": bytes_launch / per_launch_s / 1e9, "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s", "frac": b_frac}
+        other = {"bound": "mfma", "achieved": flops_launch / per_launch_s / 1e12, "peak": mfma_peak / 1e12,
+                 "unit": "TFLOP/s", "frac": f_frac}
+    else:
+        roof = {"bound": "mfma", "achieved": flops_launch / per_launch_s / 1e12, "peak": mfma_peak / 1e12,
+                "unit": "TFLOP/s", "frac": f_frac}
+        other = {"bound": "hbm", "achieved": bytes_launch / per_launch_s / 1e9, "peak": HBM_PEAK / 1e9,
+                 "unit": "GB/s", "frac": b_frac}
+    roof["traffic"] = traffic
+    roof.update({
+        "kernel": kern,
+        "launches_per_step": launches_per_step,
+        "avg_launch_ms": per_launch_s * 1e3,
+        "algorithmic_flops_per_launch": flops_launch,
+        "algorithmic_bytes_per_launch": bytes_launch,
+        "other_bound": other,
+        "stage_ms_per_step": {s: v[0] / args.steps for s, v in stages.items()},
+    })
     out = {
-        "metric": "HDMR-ASG point x output evals/sec at d=100, m=51 (%s)" %
-                  ("plain FP64" if prec == hd.PLAIN_FP64 else "mixed"),
+        "metric": "HDMR-ASG point x output evaluations/sec at d=100, m=51",
         "value": value,
         "unit": "point*outputs/s",
         "n_gpus": 1,
@@ -97,30 +179,19 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == hd.PLAIN_FP64 else "f32/bf16x3/f64",
+        "dtype": "f64" if prec == hd.PLAIN_FP64 else "f32 basis, bf16x3 mfma, f64 sum",
         "data": "synthetic",
         "config": {
             "workload": "%s: d=%d, %d components (%d one-dim + %d two-dim), adaptive sparse grids max level %d "
-                        "eps_gamma=%g, m=%d, %d next-state points" %
+                        "eps_gamma=%g, m=%d, %d next-state points, %s precision" %
                         (args.config, d, info["n_components"], d, info["n_components"] - d, cfg["max_level"],
-                         cfg["eps_gamma"], m, n),
+                         cfg["eps_gamma"], m, n, args.precision),
             "grid_rows": info["n_rows"],
             "nonzeros_per_point": hits / n,
             "lookups_per_point": probes / n,
             "parallelism": "single GPU (points)",
         },
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved / 1e12,
-            "peak": FP64_PEAK / 1e12,
-            "unit": "TFLOP/s",
-            "frac": achieved / FP64_PEAK,
-            "traffic": None,
-            "kernel": "k_pass_mfma (cell-sorted FP64 MFMA contraction, one launch per 32 outputs per pass)"
-                      if prec == hd.PLAIN_FP64 else "mixed",
-            "algorithmic_flops_per_launch": flops,
-            "algorithmic_hbm_bytes_per_launch": float(n * d * 8 + n * m * 8 + info["device_bytes"]),
-        },
+        "roofline": roof,
         "wall_s_timed_region": wall,
     }
     if not args.no_cpu_baseline:
@@ -132,8 +203,6 @@ def main():
 def cpu_baseline(cfg, sample, ws):
     """The FP64 oracle (C, OpenMP over points, level-wise mode) on its own build
     of the same workload, timed on this host's cores on a bounded sample."""
-    import numpy as np
-
     import oracle
     tf = ws.test_function_for(cfg)
     t0 = time.time()
@@ -148,7 +217,7 @@ def cpu_baseline(cfg, sample, ws):
     log("oracle eval of %d points: %.2f s" % (sample, t))
     return {"value": sample * cfg["m"] / t, "unit": "point*outputs/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": "%d of the %d next-state points (seed %d), level-wise FP64 oracle with compensated sums"
+            "sample": "first %d of the %d next-state points (seed %d), level-wise FP64 oracle with compensated sums"
                       % (sample, cfg["n"], cfg["seed"])}
 
 

@@ -140,6 +140,8 @@ typedef struct {
   int64_t device_bytes;         /* device memory the model holds                   */
   int32_t max_level;            /* largest level in any dimension                   */
   int32_t max_k;                /* largest |S|                                      */
+  int32_t n_passes;             /* passes of the cell-sorted evaluation             */
+  int32_t pass_key_dims;        /* key dimensions summed over the passes            */
 } hdmr_model_info;
 
 int hdmr_get_info(const hdmr_model *model, hdmr_model_info *info);
@@ -152,6 +154,21 @@ int hdmr_export_component(const hdmr_model *model, int32_t comp, int64_t *npts, 
                           uint8_t *levels, uint32_t *indices, double *surpluses, double *weight);
 
 void hdmr_free(hdmr_model *model);
+
+/* Per-kernel device timing (diagnostic; not part of the method).  While
+ * enabled, the evaluation brackets each stage of every pass with device
+ * events recorded on the launch stream.  The stages are:
+ *   "sort"     -- keys, radix sort, cell bounds, tiles, sorted coordinates;
+ *   "rows"     -- per-cell row discovery: count, scan, write;
+ *   "contract" -- the matrix-core contraction of the tiles.
+ * hdmr_timing_enable(on): on != 0 enables timing and discards earlier
+ * records; on == 0 disables it and discards them.
+ * hdmr_timing_read(stage, total_ms, launches) waits for the recorded events
+ * and returns the summed device time (ms) and the number of bracketed launches
+ * of that stage since enabling.  Unknown stage names give HDMR_EINVAL.
+ * Calls from several threads are serialised. */
+int hdmr_timing_enable(int32_t on);
+int hdmr_timing_read(const char *stage, double *total_ms, int64_t *launches);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char *hdmr_last_error(void);

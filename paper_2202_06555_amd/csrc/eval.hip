@@ -371,9 +371,6 @@ using namespace hdmr;
 
 extern "C" {
 
-__attribute__((visibility("hidden"))) int hdmr_eval_mixed_impl(const hdmr_model *model, const double *points,
-                                                             int64_t n, double *values, hipStream_t stream);
-
 int hdmr_eval(const hdmr_model *model, const double *points, int64_t n, double *values, int32_t m,
               int32_t precision, hdmr_stream_t stream_) {
   clear_error();
@@ -383,8 +380,8 @@ int hdmr_eval(const hdmr_model *model, const double *points, int64_t n, double *
   if (n == 0) return HDMR_OK;
   if ((rc = set_device_of(model))) return rc;
   hipStream_t stream = (hipStream_t)stream_;
-  if (precision == HDMR_MIXED) return hdmr_eval_mixed_impl(model, points, n, values, stream);
-  if (use_sorted_path(model, n)) return eval_sorted_fp64(model, points, n, values, stream);
+  if (precision == HDMR_MIXED) return eval_sorted(model, points, n, values, HDMR_MIXED, stream);
+  if (use_sorted_path(model, n)) return eval_sorted(model, points, n, values, HDMR_PLAIN_FP64, stream);
   const ModelView M = model->view();
   const size_t per = ((size_t)M.d * 8 + 64 * 8 + 64 * 4 + 15) & ~(size_t)15;
   const size_t smem = per * WAVES_PER_BLOCK;

@@ -1,21 +1,25 @@
-// Cell-sorted evaluation (the large-batch path of hdmr_eval, FP64).
+// Cell-sorted evaluation: the large-batch path of hdmr_eval (plain FP64) and
+// the whole mixed-precision path.
 //
 // Every point of one finest cell of a component's dimensions activates
-// exactly the same rows (one odd index per level and dimension, eq (3.3)).
-// Per pass (one component of the largest order plus the lower-order
-// components inside its dimensions):
-//   keys    : the cell of every point in the key dimensions (<= 16 bits);
-//   sort    : radix sort of (key, point) pairs, so points of one cell are
-//             neighbours in the sorted order;
-//   contract: a wavefront takes 64 consecutive sorted points, one per lane.
-//             Per level multi-index of the pass (a wave-uniform loop) every
-//             lane finds its active cell, its basis weight w = w_S prod phi
-//             (eq (3.1), eq (3.2)) and its row through the directory, and
-//             accumulates w * alpha[row, :] (eq (3.6)) in FP64 registers.
-//             Lanes of one cell read the same directory entries and surplus
-//             rows, so these loads are served once per wave from L1.  The
-//             sum is added to the point's FP64 output row (the first pass
-//             writes c0 + sum).
+// exactly the same rows (one odd index per level and dimension, eq (3.3)),
+// so the evaluation of eq (3.6) over a batch of points becomes, per cell, a
+// small dense product W (points x rows) * A (rows x outputs).  Per pass (one
+// component of the largest order plus the lower-order components inside its
+// dimensions):
+//   keys     : the cell of every point in the key dimensions (<= 16 bits);
+//   sort     : radix sort of (key, point) pairs, so the points of a cell are
+//              neighbours; cell bounds; tiles of <= 64 points of one cell;
+//   rows     : the rows of every nonempty cell through the directory
+//              (count, exclusive scan, write: a CSR of (cell, row));
+//   contract : a workgroup per tile stages the tile's rows, the basis weights
+//              W = w_S prod phi (eq (3.1), eq (3.2)) and the surplus rows in
+//              LDS and multiplies them on the matrix cores; the per-point
+//              sums are added to the FP64 output rows (the first pass writes
+//              c0 + sum).
+// Plain: FP64 weights and surpluses, FP64 MFMA, FP64 accumulation.  Mixed:
+// FP32 weights and surpluses split into three BF16 terms, BF16 MFMA with FP32
+// accumulation per pass, FP64 accumulation across passes and of c0.
 // Before the passes the points are transposed to dimension-major order (a
 // pass reads only its key columns) and NaN points are flagged; after them
 // flagged points get NaN outputs.
@@ -29,11 +33,6 @@
 namespace hdmr {
 
 namespace {
-
-constexpr int RBATCH = 64;           // rows contracted per batch
-constexpr int CELLCAP = RBATCH + 64; // discovered rows held in LDS per wave
-
-
 
 __global__ void k_transpose(const double *__restrict__ X, int64_t n, int d, double *__restrict__ XT,
                             uint8_t *__restrict__ nanflag) {
@@ -90,13 +89,14 @@ __global__ void k_gather_sorted(const double *__restrict__ XT, int64_t n, Pass P
   }
 }
 
+__global__ void k_write_c0(double *__restrict__ F, const double *__restrict__ c0, int64_t n, int m) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * m; i += (int64_t)gridDim.x * blockDim.x)
+    F[i] = c0[i % m];
+}
+
 __global__ void k_nan_fix(double *__restrict__ F, const uint8_t *__restrict__ nanflag, int64_t n, int m) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * m; e += (int64_t)gridDim.x * blockDim.x)
     if (nanflag[e / m]) F[e] = __builtin_nan("");
-}
-
-__device__ __forceinline__ double pick(const double (&x)[KMAX], int pos) {
-  return pos == 0 ? x[0] : pos == 1 ? x[1] : pos == 2 ? x[2] : x[3];
 }
 
 // Cell bounds from the sorted keys: [start, end) of every nonempty cell.
@@ -115,245 +115,496 @@ __global__ void k_tile_counts(const uint32_t *__restrict__ start, const uint32_t
   if (b < nbins) ntile[b] = (end[b] - start[b] + WAVE - 1) / WAVE;
 }
 
+// Tiles of <= 64 consecutive sorted points of one cell: (first sorted point,
+// count, rows of the cell, first CSR entry of the cell).
 __global__ void k_write_tiles(const uint32_t *__restrict__ start, const uint32_t *__restrict__ end,
-                              const uint32_t *__restrict__ ntile, const uint32_t *__restrict__ toff, int nbins,
-                              int4 *__restrict__ tiles, uint32_t *__restrict__ ntiles) {
+                              const uint32_t *__restrict__ ntile, const uint32_t *__restrict__ toff,
+                              const uint32_t *__restrict__ crows, const uint32_t *__restrict__ coff, int nbins,
+                              uint4 *__restrict__ tiles, uint32_t *__restrict__ ntiles) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nbins) return;
   const uint32_t s0 = start[b], cnt = end[b] - start[b];
   for (uint32_t t = 0; t < ntile[b]; ++t)
-    tiles[toff[b] + t] = make_int4(b, (int)(s0 + t * WAVE), (int)min(cnt - t * WAVE, (uint32_t)WAVE), 0);
+    tiles[toff[b] + t] = make_uint4(s0 + t * WAVE, min(cnt - t * WAVE, (uint32_t)WAVE), crows[b], coff[b]);
   if (b == nbins - 1) *ntiles = toff[b] + ntile[b];
 }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// The rows of a cell as found by the discovery step.
-struct CellRows {
-  double w[CELLCAP];            // w_S
-  double sc[CELLCAP][KMAX];     // 2^l per dimension
-  double ix[CELLCAP][KMAX];     // i per dimension
-  int32_t row[CELLCAP];
-  int32_t k[CELLCAP];
-  int32_t pos[CELLCAP][KMAX];   // key position of each dimension
+// A row of a cell as the contraction needs it (32 bytes).
+struct alignas(16) CellRow {
+  int32_t row;
+  float w;          // w_S (exact: 1 or an integer of eq (4.2))
+  uint8_t k, pad0, pad1, pad2;
+  uint8_t pos[KMAX];
+  uint8_t lv[KMAX];
+  uint16_t ixs[KMAX]; // unused padding keeps 16-byte alignment
 };
 
-struct TileLds {
-  CellRows rows;
-  double xs[WAVE][KMAX];
-  int32_t pid[WAVE];
-};
-
-// One wavefront per tile (<= 64 sorted points of one cell).
-//   discovery: lanes over the pass's level multi-indices find the cell's rows
-//     (one candidate cell per level multi-index, more when the cell is coarser
-//     than the level), ballot + prefix compaction into LDS;
-//   operands : the rows' surpluses for the wave's 16-output column tiles go
-//     straight into the MFMA B-operand registers in one burst (each lane
-//     holds distinct elements: 4 rows x 16 columns per k-step and tile);
-//   contract : per 16-point row tile, each lane forms its A-operand weight
-//     w = w_S prod phi (eq (3.1), eq (3.2)) for (point, row) and the wave
-//     runs FP64 MFMA 16x16x4 over the cell's rows (eq (3.6));
-//   update   : the 16 x 16 output tiles are added to the FP64 output rows
-//     (prefetched before the MFMAs; the first pass writes c0 + sum).
-template <int NT>
-__global__ __launch_bounds__(256, 2) void k_pass_mfma(ModelView M, Pass P, const PassTup *__restrict__ ptups,
-                                                   const int4 *__restrict__ tiles, const uint32_t *__restrict__ ntiles_p,
-                                                   const int32_t *__restrict__ spid, const double *__restrict__ sx,
-                                                   int64_t n, double *__restrict__ F, int first_pass, int o0) {
-  constexpr int KS = RBATCH / 4;   // k-steps per batch
-  __shared__ TileLds lds[WAVES_PER_BLOCK];
+// Discovery of the rows of every nonempty cell of a pass: one wavefront per
+// cell, lanes over the pass's level multi-indices (one candidate basis
+// function per level multi-index, 2^(l-c-1) per dimension where the level l
+// is finer than the cell level c), directory lookup, ballot + prefix
+// compaction.  Count mode (off == NULL): nrows[cell] = number of rows (0 for
+// empty cells).  Write mode: row r of the cell goes to list[off[cell] + r],
+// its odd indices to idx[off[cell] + r].
+__global__ __launch_bounds__(256) void k_cell_rows(ModelView M, Pass P, const PassTup *__restrict__ ptups,
+                                                   const uint32_t *__restrict__ bstart,
+                                                   const uint32_t *__restrict__ bend, int nbins,
+                                                   const uint32_t *__restrict__ off, CellRow *__restrict__ list,
+                                                   uint4 *__restrict__ idx, uint32_t *__restrict__ nrows_out) {
   const int lane = threadIdx.x & (WAVE - 1);
-  const int wid = threadIdx.x / WAVE;
-  TileLds &L = lds[wid];
-  const int m = M.m;
-  const int kk = lane >> 4, jj = lane & 15;
-  const uint32_t ntiles = *ntiles_p;
   const int64_t nw = (int64_t)gridDim.x * WAVES_PER_BLOCK;
-  for (int64_t ti = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wid; ti < (int64_t)ntiles; ti += nw) {
-    const int4 tile = tiles[ti];
-    const uint32_t key = (uint32_t)tile.x;
-    const int start = tile.y, count = tile.z;
-    {
-      const int32_t pid = lane < count ? spid[start + lane] : 0;
-      L.pid[lane] = pid;
-#pragma unroll
-      for (int q = 0; q < KMAX; ++q) L.xs[lane][q] = (lane < count && q < P.k) ? sx[(int64_t)q * n + start + lane] : 0.0;
+  for (int64_t bin = (int64_t)blockIdx.x * WAVES_PER_BLOCK + threadIdx.x / WAVE; bin < nbins; bin += nw) {
+    if (bend[bin] <= bstart[bin]) {
+      if (!off && lane == 0) nrows_out[bin] = 0;
+      continue;
     }
+    const uint32_t base = off ? off[bin] : 0u;
+    const uint32_t key = (uint32_t)bin;
     uint32_t cellq[KMAX];
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) cellq[q] = q < P.k ? (key >> P.shift[q]) & ((1u << P.cell_lv[q]) - 1u) : 0u;
-    bool first = first_pass != 0;
-    int rb0 = P.tup_begin;
-    uint32_t rcand = 0;
-    bool done = rb0 >= P.tup_end;
     int nrows = 0;
-    for (;;) {
-      // ---- discovery (resumable) until a batch of RBATCH rows is complete ----
-      while (!done && nrows < RBATCH) {
-        const int j = rb0 + lane;
-        TupDesc T{};
-        PassTup PT{};
-        uint32_t lo[KMAX] = {0, 0, 0, 0}, cnt[KMAX] = {1, 1, 1, 1}, ncand = 0;
-        if (j < P.tup_end) {
-          PT = ptups[j];
-          T = M.tups[PT.tup];
-          ncand = 1;
+    for (int b0 = P.tup_begin; b0 < P.tup_end; b0 += WAVE) {
+      const int j = b0 + lane;
+      TupDesc T{};
+      PassTup PT{};
+      uint32_t lo[KMAX] = {0, 0, 0, 0}, cnt[KMAX] = {1, 1, 1, 1}, ncand = 0;
+      if (j < P.tup_end) {
+        PT = ptups[j];
+        T = M.tups[PT.tup];
+        ncand = 1;
 #pragma unroll
-          for (int q = 0; q < KMAX; ++q) {
-            if (q < T.k) {
-              const int c = P.cell_lv[PT.pos[q]], l = T.lv[q];
-              const uint32_t cell = cellq[PT.pos[q]];
-              if (l <= c) {
-                lo[q] = (cell >> (c - l)) >> 1;
-                cnt[q] = 1;
-              } else {
-                lo[q] = (cell << (l - c)) >> 1;
-                cnt[q] = 1u << (l - c - 1);
-              }
-              ncand *= cnt[q];
+        for (int q = 0; q < KMAX; ++q) {
+          if (q < T.k) {
+            const int c = P.cell_lv[PT.pos[q]], l = T.lv[q];
+            const uint32_t cell = cellq[PT.pos[q]];
+            if (l <= c) {
+              lo[q] = (cell >> (c - l)) >> 1;
+              cnt[q] = 1;
+            } else {
+              lo[q] = (cell << (l - c)) >> 1;
+              cnt[q] = 1u << (l - c - 1);
             }
+            ncand *= cnt[q];
           }
         }
-        uint32_t maxc = ncand;
+      }
+      uint32_t maxc = ncand;
 #pragma unroll
-        for (int off = 1; off < WAVE; off <<= 1) maxc = max(maxc, (uint32_t)__shfl_xor((int)maxc, off, WAVE));
-        uint32_t cand = rcand;
-        for (; cand < maxc && nrows < RBATCH; ++cand) {
-          int32_t row = -1;
-          uint32_t half[KMAX] = {0, 0, 0, 0};
-          if (cand < ncand) {
-            uint32_t rem = cand, slot = 0;
+      for (int off = 1; off < WAVE; off <<= 1) maxc = max(maxc, (uint32_t)__shfl_xor((int)maxc, off, WAVE));
+      for (uint32_t cand = 0; cand < maxc; ++cand) {
+        int32_t row = -1;
+        uint32_t half[KMAX] = {0, 0, 0, 0};
+        if (cand < ncand) {
+          uint32_t rem = cand, slot = 0;
 #pragma unroll
-            for (int q = KMAX - 1; q >= 0; --q)
-              if (q < T.k) {
-                half[q] = lo[q] + rem % cnt[q];
-                rem /= cnt[q];
-              }
+          for (int q = KMAX - 1; q >= 0; --q)
+            if (q < T.k) {
+              half[q] = lo[q] + rem % cnt[q];
+              rem /= cnt[q];
+            }
 #pragma unroll
-            for (int q = 0; q < KMAX; ++q)
-              if (q < T.k) slot = (slot << (T.lv[q] - 1)) | half[q];
-            row = lookup_row(T, slot, M.tab);
-          }
-          const bool hit = row >= 0;
-          const uint64_t mask = ballot(hit);
-          if (hit) {
-            const int e = nrows + lanes_below(mask);
-            L.rows.w[e] = T.w;
-            L.rows.row[e] = row;
-            L.rows.k[e] = T.k;
+          for (int q = 0; q < KMAX; ++q)
+            if (q < T.k) slot = (slot << (T.lv[q] - 1)) | half[q];
+          row = lookup_row(T, slot, M.tab);
+        }
+        const bool hit = row >= 0;
+        const uint64_t mask = ballot(hit);
+        if (hit && off) {
+          const uint32_t e = base + (uint32_t)(nrows + lanes_below(mask));
+          {
+            CellRow R{};
+            R.row = row;
+            R.w = (float)T.w;
+            R.k = T.k;
+            uint4 ix;
 #pragma unroll
             for (int q = 0; q < KMAX; ++q) {
-              L.rows.pos[e][q] = PT.pos[q];
-              L.rows.sc[e][q] = (double)(1u << (T.lv[q] ? T.lv[q] : 1));
-              L.rows.ix[e][q] = (double)(2u * half[q] + 1u);
+              R.pos[q] = PT.pos[q];
+              R.lv[q] = T.lv[q];
             }
+            ix.x = 2u * half[0] + 1u;
+            ix.y = 2u * half[1] + 1u;
+            ix.z = 2u * half[2] + 1u;
+            ix.w = 2u * half[3] + 1u;
+            list[e] = R;
+            idx[e] = ix;
           }
-          nrows += __popcll(mask);
         }
-        if (cand < maxc) {
-          rcand = cand;
-        } else {
-          rcand = 0;
-          rb0 += WAVE;
-          done = rb0 >= P.tup_end;
-        }
+        nrows += __popcll(mask);
       }
-      wave_sync();
-      const int R = min(nrows, RBATCH);
-      if (R > 0 || (done && first)) {
-        const int Rp = (R + 3) & ~3;
-        // B operands of the whole batch, one burst
-        double b[KS][NT];
-#pragma unroll
-        for (int s4 = 0; s4 < KS; ++s4) {
-          const int r = s4 * 4 + kk;
-          const int32_t row = r < R ? L.rows.row[r] : -1;
-#pragma unroll
-          for (int nt = 0; nt < NT; ++nt) {
-            const int o = o0 + nt * 16 + jj;
-            b[s4][nt] = (row >= 0 && o < m) ? M.alpha[(int64_t)row * M.ms + o] : 0.0;
-          }
-        }
-        const int nmt = (count + 15) >> 4;
-        for (int mt = 0; mt < nmt; ++mt) {
-          v4d acc[NT];
-#pragma unroll
-          for (int nt = 0; nt < NT; ++nt) acc[nt] = v4d{0.0, 0.0, 0.0, 0.0};
-          const int pa = mt * 16 + jj;   // this lane's A-operand point
-#pragma unroll
-          for (int s4 = 0; s4 < KS; ++s4) {
-            if (s4 * 4 < Rp) {
-              const int r = s4 * 4 + kk;
-              double w = 0.0;
-              if (r < R && pa < count) {
-                w = L.rows.w[r];
-                const int k = L.rows.k[r];
-#pragma unroll
-                for (int q = 0; q < KMAX; ++q)
-                  if (q < k) w *= fmax(0.0, 1.0 - fabs(L.xs[pa][L.rows.pos[r][q]] * L.rows.sc[r][q] - L.rows.ix[r][q]));
-              }
-#pragma unroll
-              for (int nt = 0; nt < NT; ++nt) acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(w, b[s4][nt], acc[nt], 0, 0, 0);
-            }
-          }
-          // the first contraction of a point writes c0 + sum; later ones add
-          // with device atomics (no value returned, so the wave never waits;
-          // one tile owns a point within a pass, passes run in order)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int pt = mt * 16 + kk + 4 * i;
-            if (pt < count) {
-              double *fr = F + (int64_t)L.pid[pt] * m;
-#pragma unroll
-              for (int nt = 0; nt < NT; ++nt) {
-                const int o = o0 + nt * 16 + jj;
-                if (o < m) {
-                  if (first)
-                    fr[o] = M.c0[o] + acc[nt][i];
-                  else
-                    atomicAdd(fr + o, acc[nt][i]);
-                }
-              }
-            }
-          }
-        }
-        first = false;
-      }
-      // rows past the batch move to the front
-      const int rest = nrows - R;
-      if (rest > 0) {
-        double tw = 0.0, tsc[KMAX], tix[KMAX];
-        int32_t trow = 0, tk = 0, tpos[KMAX];
-        if (lane < rest) {
-          const int e = R + lane;
-          tw = L.rows.w[e];
-          trow = L.rows.row[e];
-          tk = L.rows.k[e];
-#pragma unroll
-          for (int q = 0; q < KMAX; ++q) {
-            tsc[q] = L.rows.sc[e][q];
-            tix[q] = L.rows.ix[e][q];
-            tpos[q] = L.rows.pos[e][q];
-          }
-        }
-        wave_sync();
-        if (lane < rest) {
-          L.rows.w[lane] = tw;
-          L.rows.row[lane] = trow;
-          L.rows.k[lane] = tk;
-#pragma unroll
-          for (int q = 0; q < KMAX; ++q) {
-            L.rows.sc[lane][q] = tsc[q];
-            L.rows.ix[lane][q] = tix[q];
-            L.rows.pos[lane][q] = tpos[q];
-          }
-        }
-      }
-      wave_sync();
-      nrows = rest;
-      if (done && nrows == 0) break;
     }
+    if (!off && lane == 0) nrows_out[bin] = (uint32_t)nrows;
+  }
+}
+
+// Basis weight of a point (coordinates xs[pos]) for one stored row:
+// w_S prod_q max(0, 1 - |x 2^l - i|) (eq (3.1), eq (3.2)); x 2^l - i is exact
+// in FP64.
+// Basis weight of a point with key coordinates x0..x3 for one stored row:
+// w_S prod_q max(0, 1 - |x 2^l - i|) (eq (3.1), eq (3.2)); x 2^l - i is exact
+// in FP64.  (Scalar arguments: a selected element of a local array would be
+// lowered to an indexed load from scratch memory.)
+__device__ __forceinline__ double row_weight(const CellRow &R, const uint4 &ix, double x0, double x1, double x2,
+                                             double x3) {
+  const uint32_t iv[KMAX] = {ix.x, ix.y, ix.z, ix.w};
+  double w = (double)R.w;
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    if (q < R.k) {
+      const int p = R.pos[q];
+      double x = x0;
+      x = p == 1 ? x1 : x;
+      x = p == 2 ? x2 : x;
+      x = p == 3 ? x3 : x;
+      w *= fmax(0.0, 1.0 - fabs(x * (double)(1u << R.lv[q]) - (double)iv[q]));
+    }
+  }
+  return w;
+}
+
+constexpr int TPTS = 64;  // points per tile (one MFMA row tile per 16)
+#ifndef HDMR_TR_FP64
+#define HDMR_TR_FP64 48
+#endif
+#ifndef HDMR_TR_MIXED
+#define HDMR_TR_MIXED 64
+#endif
+#ifndef HDMR_TILE_GRID
+#define HDMR_TILE_GRID 4096
+#endif
+constexpr int TR_FP64 = HDMR_TR_FP64;    // rows per batch, FP64 contraction
+constexpr int TR_MIXED = HDMR_TR_MIXED;  // rows per batch, mixed contraction
+constexpr int TILE_GRID = HDMR_TILE_GRID;  // workgroups of a contraction launch
+
+// Per-thread staging registers of one tile: thread t < count holds point t
+// (id and key coordinates), thread t < min(rows, TR) holds row t of the cell.
+// (Scalar and native vector members only: arrays, or HIP's uint4 with its
+// union storage, in a per-thread struct end up in scratch memory.)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+struct TileRegs {
+  int32_t pid;
+  double x0, x1, x2, x3;
+  u32x4 row0, row1;  // the CellRow, as two 16-byte words
+  u32x4 ix;
+};
+static_assert(sizeof(CellRow) == 32, "CellRow is staged as two 16-byte words");
+
+template <int TR>
+__device__ __forceinline__ void fetch_tile(const uint4 &rec, int t, int k, const int32_t *__restrict__ spid,
+                                           const double *__restrict__ sx, int64_t n,
+                                           const CellRow *__restrict__ list, const uint4 *__restrict__ idx,
+                                           TileRegs &g) {
+  const uint32_t start = rec.x, count = rec.y, R = rec.z, base = rec.w;
+  if ((uint32_t)t < count) {
+    g.pid = spid[start + t];
+    const double *p = sx + start + t;
+    g.x0 = p[0];
+    g.x1 = k > 1 ? p[n] : 0.0;
+    g.x2 = k > 2 ? p[2 * n] : 0.0;
+    g.x3 = k > 3 ? p[3 * n] : 0.0;
+  }
+  if ((uint32_t)t < min(R, (uint32_t)TR)) {
+    const u32x4 *src = reinterpret_cast<const u32x4 *>(list + (int64_t)base + t);
+    g.row0 = src[0];
+    g.row1 = src[1];
+    g.ix = *reinterpret_cast<const u32x4 *>(idx + (int64_t)base + t);
+  }
+}
+
+// Tile record i, or an empty record past the end (a value select: a
+// conditional load would become a load through a selected pointer).
+__device__ __forceinline__ uint4 tile_rec(const uint4 *__restrict__ tiles, int64_t i, int64_t ntiles) {
+  const uint4 v = tiles[i < ntiles ? i : ntiles - 1];
+  const bool in = i < ntiles;
+  return make_uint4(in ? v.x : 0u, in ? v.y : 0u, in ? v.z : 0u, in ? v.w : 0u);
+}
+
+// Tile meta in LDS (double-buffered: the next tile's is written while the
+// current one is contracted).
+template <int TR>
+struct TileMeta {
+  CellRow rows[TR];
+  uint4 ix[TR];
+  double xs[TPTS][KMAX];
+  int32_t pid[TPTS];
+};
+
+template <int TR>
+__device__ __forceinline__ void store_tile(TileMeta<TR> &S, const TileRegs &g, int t) {
+  if (t < TPTS) {
+    S.pid[t] = g.pid;
+    S.xs[t][0] = g.x0;
+    S.xs[t][1] = g.x1;
+    S.xs[t][2] = g.x2;
+    S.xs[t][3] = g.x3;
+  }
+  if (t < TR) {
+    u32x4 *dst = reinterpret_cast<u32x4 *>(&S.rows[t]);
+    dst[0] = g.row0;
+    dst[1] = g.row1;
+    *reinterpret_cast<u32x4 *>(&S.ix[t]) = g.ix;
+  }
+}
+
+// Plain FP64 contraction.  A workgroup of 4 waves takes one tile at a time
+// (grid-stride over the tiles); wave w owns the 16 outputs o0 + 16w ..; the
+// basis weights W (64 points x TR rows of the cell) are formed once in LDS
+// and shared by the waves (MFMA A operand); each wave loads its own surplus
+// slice (B operand) straight into registers.  The next tile's points and
+// first rows are loaded at the start of a tile and parked in the other LDS
+// buffer before the MFMA phase.  The per-point sums go to the FP64 outputs:
+// the first pass writes c0 + sum, later passes add with device atomics (each
+// (point, output) has one writer per pass).
+template <int TR>
+__global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const uint4 *__restrict__ tiles,
+                                                      const uint32_t *__restrict__ ntiles_p,
+                                                      const CellRow *__restrict__ list, const uint4 *__restrict__ idx,
+                                                      const int32_t *__restrict__ spid, const double *__restrict__ sx,
+                                                      int64_t n, double *__restrict__ F, int first, int o0) {
+  constexpr int WS = TR + 4;  // W row stride (doubles): spreads A-operand reads over the LDS banks
+  __shared__ double s_w[TPTS][WS];
+  __shared__ TileMeta<TR> s_meta[2];
+  const int t = threadIdx.x, lane = t & (WAVE - 1), wid = t / WAVE;
+  const int kk = lane >> 4, jj = lane & 15;
+  const int m = M.m;
+  const int col = o0 + wid * 16 + jj;
+  const bool wave_on = o0 + wid * 16 < m;
+  const int64_t ntiles = *ntiles_p;
+  if (ntiles == 0) return;
+  int64_t ti = blockIdx.x;
+  uint4 rec = tile_rec(tiles, ti, ntiles);
+  uint4 rec_n = tile_rec(tiles, ti + gridDim.x, ntiles);
+  {
+    TileRegs g{};
+    fetch_tile<TR>(rec, t, P.k, spid, sx, n, list, idx, g);
+    store_tile<TR>(s_meta[0], g, t);
+  }
+  int cur = 0;
+  for (; ti < ntiles; ti += gridDim.x) {
+    const int count = (int)rec.y, R = (int)rec.z;
+    const uint32_t base = rec.w;
+    const uint4 rec_nn = tile_rec(tiles, ti + 2 * (int64_t)gridDim.x, ntiles);
+    __syncthreads();  // the previous tile is done with s_w and its meta buffer
+    TileRegs g{};
+    fetch_tile<TR>(rec_n, t, P.k, spid, sx, n, list, idx, g);
+    TileMeta<TR> &S = s_meta[cur];
+    const bool work = !(R == 0 && !first);  // nothing to add otherwise (uniform)
+    v4d acc[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) acc[mt] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int nbat = work ? max(1, (R + TR - 1) / TR) : 0;
+    for (int bt = 0; bt < nbat; ++bt) {
+      const int Rb = min(TR, R - bt * TR);
+      const int Rp = (Rb + 3) & ~3;
+      if (bt > 0) {
+        __syncthreads();  // the previous batch is done with s_w and the rows
+        if (t < Rb) {
+          S.rows[t] = list[(int64_t)base + bt * TR + t];
+          S.ix[t] = idx[(int64_t)base + bt * TR + t];
+        }
+        __syncthreads();
+      }
+      // B operand: rows 4j + kk of the batch, this lane's output column
+      double b[TR / 4];
+#pragma unroll
+      for (int j = 0; j < TR / 4; ++j) {
+        const int r = 4 * j + kk;
+        b[j] = (r < Rb && col < m) ? M.alpha[(int64_t)S.rows[r].row * M.ms + col] : 0.0;
+      }
+      // W: thread (pt = t / 4, group t % 4) forms rows group, group + 4, ...
+      {
+        const int pt = t >> 2, grp = t & 3;
+        const double x0 = S.xs[pt][0], x1 = S.xs[pt][1], x2 = S.xs[pt][2], x3 = S.xs[pt][3];
+#pragma unroll 2
+        for (int r = grp; r < Rp; r += 4)
+          s_w[pt][r] = (r < Rb && pt < count) ? row_weight(S.rows[r], S.ix[r], x0, x1, x2, x3) : 0.0;
+      }
+      if (bt == 0) store_tile<TR>(s_meta[cur ^ 1], g, t);
+      __syncthreads();
+      if (wave_on) {
+#pragma unroll
+        for (int j = 0; j < TR / 4; ++j) {
+          if (4 * j < Rp) {
+            // padded points (pt >= count) have zero weights
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+              acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[mt * 16 + jj][4 * j + kk], b[j], acc[mt], 0, 0, 0);
+            // bound how far A-operand loads are hoisted (register pressure)
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+      }
+    }
+    if (!work) store_tile<TR>(s_meta[cur ^ 1], g, t);
+    // lane holds rows kk + 4 i of each 16-point tile, column jj
+    if (work && wave_on && col < m) {
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int pt = mt * 16 + kk + 4 * i;
+          if (pt < count) {
+            double *dst = F + (int64_t)S.pid[pt] * m + col;
+            if (first)
+              *dst = M.c0[col] + acc[mt][i];
+            else
+              atomicAdd(dst, acc[mt][i]);
+          }
+        }
+    }
+    rec = rec_n;
+    rec_n = rec_nn;
+    cur ^= 1;
+  }
+}
+
+// Split of an FP32 value into three BF16 terms, v = hi + mid + lo (exact for
+// normal FP32 values: each term takes the next 8 significant bits).
+__device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &mid, __bf16 &lo) {
+  hi = (__bf16)v;
+  const float r1 = v - (float)hi;
+  mid = (__bf16)r1;
+  lo = (__bf16)(r1 - (float)mid);
+}
+
+// Mixed-precision contraction, same tiling as the FP64 kernel: weights are
+// formed in FP64 (exact x 2^l - i) and rounded to FP32, surpluses are the
+// model's FP32 copy; both are split into three BF16 terms and multiplied on
+// BF16 MFMA 16x16x32 with FP32 accumulation, keeping the six products
+// hi*hi, hi*mid, mid*hi, hi*lo, mid*mid, lo*hi (the dropped ones are below
+// 2^-24 relative).  The per-point FP32 sums of the pass are added to the
+// FP64 outputs (c0 and the sum over passes stay FP64).
+template <int TR>
+__global__ __launch_bounds__(256, 4) void k_tile_mixed(ModelView M, Pass P, const uint4 *__restrict__ tiles,
+                                                       const uint32_t *__restrict__ ntiles_p,
+                                                       const CellRow *__restrict__ list,
+                                                       const uint4 *__restrict__ idx,
+                                                       const int32_t *__restrict__ spid,
+                                                       const double *__restrict__ sx,
+                                                       const float *__restrict__ alpha32, int64_t n,
+                                                       double *__restrict__ F, int first, int o0) {
+  static_assert(TR % 32 == 0, "rows per batch: a multiple of the MFMA depth");
+  constexpr int WS = TR + 8;  // W row stride (bf16), 16-byte aligned rows
+  __shared__ __attribute__((aligned(16))) __bf16 s_w[3][TPTS][WS];
+  __shared__ TileMeta<TR> s_meta[2];
+  const int t = threadIdx.x, lane = t & (WAVE - 1), wid = t / WAVE;
+  const int kg = lane >> 4, jj = lane & 15;
+  const int m = M.m;
+  const int col = o0 + wid * 16 + jj;
+  const bool wave_on = o0 + wid * 16 < m;
+  const int64_t ntiles = *ntiles_p;
+  if (ntiles == 0) return;
+  int64_t ti = blockIdx.x;
+  uint4 rec = tile_rec(tiles, ti, ntiles);
+  uint4 rec_n = tile_rec(tiles, ti + gridDim.x, ntiles);
+  {
+    TileRegs g{};
+    fetch_tile<TR>(rec, t, P.k, spid, sx, n, list, idx, g);
+    store_tile<TR>(s_meta[0], g, t);
+  }
+  int cur = 0;
+  for (; ti < ntiles; ti += gridDim.x) {
+    const int count = (int)rec.y, R = (int)rec.z;
+    const uint32_t base = rec.w;
+    const uint4 rec_nn = tile_rec(tiles, ti + 2 * (int64_t)gridDim.x, ntiles);
+    __syncthreads();
+    TileRegs g{};
+    fetch_tile<TR>(rec_n, t, P.k, spid, sx, n, list, idx, g);
+    TileMeta<TR> &S = s_meta[cur];
+    const bool work = !(R == 0 && !first);
+    v4f acc[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) acc[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int nbat = work ? max(1, (R + TR - 1) / TR) : 0;
+    for (int bt = 0; bt < nbat; ++bt) {
+      const int Rb = min(TR, R - bt * TR);
+      const int Rp = (Rb + 31) & ~31;
+      if (bt > 0) {
+        __syncthreads();
+        if (t < Rb) {
+          S.rows[t] = list[(int64_t)base + bt * TR + t];
+          S.ix[t] = idx[(int64_t)base + bt * TR + t];
+        }
+        __syncthreads();
+      }
+      // B operand: rows 32 st + 8 kg + item of the batch, this lane's column
+      bf16x8 bh[TR / 32], bm[TR / 32], bl[TR / 32];
+#pragma unroll
+      for (int st = 0; st < TR / 32; ++st)
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+          const int r = 32 * st + 8 * kg + it;
+          const float v = (r < Rb && col < m) ? alpha32[(int64_t)S.rows[r].row * M.ms + col] : 0.f;
+          __bf16 h, md, l;
+          split_bf16(v, h, md, l);
+          bh[st][it] = h;
+          bm[st][it] = md;
+          bl[st][it] = l;
+        }
+      {
+        const int pt = t >> 2, grp = t & 3;
+        const double x0 = S.xs[pt][0], x1 = S.xs[pt][1], x2 = S.xs[pt][2], x3 = S.xs[pt][3];
+#pragma unroll 2
+        for (int r = grp; r < Rp; r += 4) {
+          const float v = (r < Rb && pt < count) ? (float)row_weight(S.rows[r], S.ix[r], x0, x1, x2, x3) : 0.f;
+          __bf16 h, md, l;
+          split_bf16(v, h, md, l);
+          s_w[0][pt][r] = h;
+          s_w[1][pt][r] = md;
+          s_w[2][pt][r] = l;
+        }
+      }
+      if (bt == 0) store_tile<TR>(s_meta[cur ^ 1], g, t);
+      __syncthreads();
+      if (wave_on) {
+#pragma unroll
+        for (int st = 0; st < TR / 32; ++st) {
+          if (32 * st < Rp) {
+            // padded points (pt >= count) have zero weights
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+              const int ro = mt * 16 + jj, ko = 32 * st + 8 * kg;
+              const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(&s_w[0][ro][ko]);
+              const bf16x8 am = *reinterpret_cast<const bf16x8 *>(&s_w[1][ro][ko]);
+              const bf16x8 al = *reinterpret_cast<const bf16x8 *>(&s_w[2][ro][ko]);
+              v4f c = acc[mt];
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[st], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[st], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[st], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[st], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm[st], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[st], c, 0, 0, 0);
+              acc[mt] = c;
+            }
+          }
+        }
+      }
+    }
+    if (!work) store_tile<TR>(s_meta[cur ^ 1], g, t);
+    // lane holds rows 4 kg + i of each 16-point tile, column jj
+    if (work && wave_on && col < m) {
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int pt = mt * 16 + 4 * kg + i;
+          if (pt < count) {
+            double *dst = F + (int64_t)S.pid[pt] * m + col;
+            if (first)
+              *dst = M.c0[col] + (double)acc[mt][i];
+            else
+              atomicAdd(dst, (double)acc[mt][i]);
+          }
+        }
+    }
+    rec = rec_n;
+    rec_n = rec_nn;
+    cur ^= 1;
   }
 }
 
@@ -365,28 +616,37 @@ int ws_alloc(T **p, size_t count, hipStream_t s) {
 
 }  // namespace
 
-int eval_sorted_fp64(const hdmr_model *model, const double *X, int64_t n, double *F, hipStream_t stream) {
+int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, int precision,
+                hipStream_t stream) {
   const ModelView M = model->view();
   const int d = M.d, m = M.m;
   if (n >= (int64_t)INT32_MAX) return fail(HDMR_EUNSUPPORTED, "n >= 2^31 points in one call");
+  if (precision == HDMR_MIXED && !model->alpha32) return fail(HDMR_EUNSUPPORTED, "model has no FP32 surpluses");
+  int64_t list_max = 1;
+  for (const Pass &P : model->passes) list_max = std::max<int64_t>(list_max, P.list_bound);
+  if (list_max >= (int64_t)UINT32_MAX) return fail(HDMR_EUNSUPPORTED, "cell row lists exceed 2^32 entries");
   double *xt = nullptr;
   uint8_t *nanflag = nullptr;
   double *sxv = nullptr;
   uint16_t *key = nullptr, *key_s = nullptr;
   int32_t *idx = nullptr, *spid = nullptr;
   uint32_t *bstart = nullptr, *bend = nullptr, *ntile = nullptr, *toff = nullptr, *ntiles = nullptr;
-  int4 *tiles = nullptr;
+  uint32_t *crows = nullptr, *coff = nullptr;
+  CellRow *clist = nullptr;
+  uint4 *cidx = nullptr;
+  uint4 *tiles = nullptr;
   void *tmp = nullptr;
   size_t tmp_sort = 0, tmp_scan = 0;
   if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_sort, key, key_s, idx, spid, (int)n, 0, 16, stream) !=
           hipSuccess ||
       hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_scan, ntile, toff, 65536, stream) != hipSuccess)
     return fail(HDMR_EDEVICE, "hipcub temporary storage query failed");
-  const size_t max_tiles = (size_t)(n / WAVE) + 65536 + 1;
+  const size_t max_tiles = (size_t)(n / TPTS) + 65536 + 1;
   const size_t tmp_bytes = std::max(tmp_sort, tmp_scan);
   int rc = HDMR_OK;
   auto release = [&]() {
-    void *ptrs[] = {xt, sxv, nanflag, key, key_s, idx, spid, bstart, bend, ntile, toff, ntiles, tiles, tmp};
+    void *ptrs[] = {xt, sxv, nanflag, key, key_s, idx, spid, bstart, bend, ntile, toff, ntiles, tiles, tmp,
+                    crows, coff, clist, cidx};
     for (void *p : ptrs) (void)hipFreeAsync(p, stream);
   };
   if ((rc = ws_alloc(&xt, (size_t)n * d, stream)) || (rc = ws_alloc(&nanflag, (size_t)n, stream)) ||
@@ -396,6 +656,8 @@ int eval_sorted_fp64(const hdmr_model *model, const double *X, int64_t n, double
       (rc = ws_alloc(&bstart, (size_t)65536, stream)) || (rc = ws_alloc(&bend, (size_t)65536, stream)) ||
       (rc = ws_alloc(&ntile, (size_t)65536, stream)) || (rc = ws_alloc(&toff, (size_t)65536, stream)) ||
       (rc = ws_alloc(&ntiles, (size_t)1, stream)) || (rc = ws_alloc(&tiles, max_tiles, stream)) ||
+      (rc = ws_alloc(&crows, (size_t)65536, stream)) || (rc = ws_alloc(&coff, (size_t)65536, stream)) ||
+      (rc = ws_alloc(&clist, (size_t)list_max, stream)) || (rc = ws_alloc(&cidx, (size_t)list_max, stream)) ||
       (rc = ws_alloc((char **)&tmp, tmp_bytes, stream))) {
     release();
     return rc;
@@ -408,32 +670,51 @@ int eval_sorted_fp64(const hdmr_model *model, const double *X, int64_t n, double
   hipError_t e = hipSuccess;
   for (const Pass &P : model->passes) {
     const int nbins = 1 << P.key_bits;
-    hipLaunchKernelGGL(k_keys, dim3(gs), dim3(256), 0, stream, xt, n, P, key, idx);
-    size_t tb = tmp_bytes;
-    e = hipcub::DeviceRadixSort::SortPairs(tmp, tb, key, key_s, idx, spid, (int)n, 0, P.key_bits, stream);
-    if (e != hipSuccess) break;
-    hipLaunchKernelGGL(k_fill_u32, dim3((nbins + 255) / 256), dim3(256), 0, stream, bstart, (int64_t)nbins);
-    hipLaunchKernelGGL(k_fill_u32, dim3((nbins + 255) / 256), dim3(256), 0, stream, bend, (int64_t)nbins);
-    hipLaunchKernelGGL(k_bounds, dim3(gs), dim3(256), 0, stream, key_s, n, bstart, bend);
-    hipLaunchKernelGGL(k_tile_counts, dim3((nbins + 255) / 256), dim3(256), 0, stream, bstart, bend, nbins, ntile);
-    tb = tmp_bytes;
-    e = hipcub::DeviceScan::ExclusiveSum(tmp, tb, ntile, toff, nbins, stream);
-    if (e != hipSuccess) break;
-    hipLaunchKernelGGL(k_write_tiles, dim3((nbins + 255) / 256), dim3(256), 0, stream, bstart, bend, ntile, toff,
-                       nbins, tiles, ntiles);
-    hipLaunchKernelGGL(k_gather_sorted, dim3(gs), dim3(256), 0, stream, xt, n, P, spid, sxv);
-    for (int o0 = 0; o0 < m; o0 += 32) {
-      const int nt = (std::min(32, m - o0) + 15) / 16;
-#define PASS(NTV)                                                                                                   \
-  hipLaunchKernelGGL(k_pass_mfma<NTV>, dim3(4096), dim3(256), 0, stream, M, P, model->pass_tups, tiles, ntiles, spid, \
-                     sxv, n, F, first, o0)
-      if (nt == 1) PASS(1);
-      else PASS(2);
-#undef PASS
+    const unsigned gb = (unsigned)((nbins + 255) / 256);
+    const unsigned gc = (unsigned)std::min((nbins + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, 8192);
+    {
+      StageTimer tm(STAGE_SORT, stream);
+      hipLaunchKernelGGL(k_keys, dim3(gs), dim3(256), 0, stream, xt, n, P, key, idx);
+      size_t tb = tmp_bytes;
+      e = hipcub::DeviceRadixSort::SortPairs(tmp, tb, key, key_s, idx, spid, (int)n, 0, P.key_bits, stream);
+      if (e != hipSuccess) break;
+      hipLaunchKernelGGL(k_fill_u32, dim3(gb), dim3(256), 0, stream, bstart, (int64_t)nbins);
+      hipLaunchKernelGGL(k_fill_u32, dim3(gb), dim3(256), 0, stream, bend, (int64_t)nbins);
+      hipLaunchKernelGGL(k_bounds, dim3(gs), dim3(256), 0, stream, key_s, n, bstart, bend);
+      hipLaunchKernelGGL(k_gather_sorted, dim3(gs), dim3(256), 0, stream, xt, n, P, spid, sxv);
+    }
+    {
+      // rows of every nonempty cell (count, offsets, write), then the tiles
+      StageTimer tm(STAGE_ROWS, stream);
+      hipLaunchKernelGGL(k_cell_rows, dim3(gc), dim3(256), 0, stream, M, P, model->pass_tups, bstart, bend, nbins,
+                         (const uint32_t *)nullptr, clist, cidx, crows);
+      size_t tb = tmp_bytes;
+      e = hipcub::DeviceScan::ExclusiveSum(tmp, tb, crows, coff, nbins, stream);
+      if (e != hipSuccess) break;
+      hipLaunchKernelGGL(k_cell_rows, dim3(gc), dim3(256), 0, stream, M, P, model->pass_tups, bstart, bend, nbins,
+                         (const uint32_t *)coff, clist, cidx, crows);
+      hipLaunchKernelGGL(k_tile_counts, dim3(gb), dim3(256), 0, stream, bstart, bend, nbins, ntile);
+      tb = tmp_bytes;
+      e = hipcub::DeviceScan::ExclusiveSum(tmp, tb, ntile, toff, nbins, stream);
+      if (e != hipSuccess) break;
+      hipLaunchKernelGGL(k_write_tiles, dim3(gb), dim3(256), 0, stream, bstart, bend, ntile, toff, crows, coff,
+                         nbins, tiles, ntiles);
+    }
+    {
+      StageTimer tm(STAGE_CONTRACT, stream);
+      for (int o0 = 0; o0 < m; o0 += 64) {
+        if (precision == HDMR_PLAIN_FP64)
+          hipLaunchKernelGGL(k_tile_fp64<TR_FP64>, dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles, clist,
+                             cidx, spid, sxv, n, F, first, o0);
+        else
+          hipLaunchKernelGGL(k_tile_mixed<TR_MIXED>, dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles,
+                             clist, cidx, spid, sxv, (const float *)model->alpha32, n, F, first, o0);
+      }
     }
     first = 0;
   }
-  if (e == hipSuccess && first) e = hipErrorInvalidValue;
+  if (e == hipSuccess && first)  // no stored rows at all: every output is c0
+    hipLaunchKernelGGL(k_write_c0, dim3(gs), dim3(256), 0, stream, F, M.c0, n, m);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_nan_fix, dim3(gs), dim3(256), 0, stream, F, nanflag, n, m);
     e = hipGetLastError();

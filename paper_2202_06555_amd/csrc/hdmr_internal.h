@@ -57,6 +57,7 @@ struct Pass {
   int32_t shift[KMAX];
   int32_t key_bits;
   int32_t tup_begin, tup_end;  // range in the pass-tuple list
+  int64_t list_bound;          // (cell, row) incidences summed over all cells
 };
 // A tuple as seen from a pass: key position of each of its dimensions.
 struct alignas(8) PassTup {
@@ -89,6 +90,7 @@ struct hdmr_model {
   hdmr::TupDesc *tups = nullptr;
   int32_t *tab = nullptr;
   double *alpha = nullptr;
+  float *alpha32 = nullptr;   // FP32 copy of alpha (same layout) for the mixed path
   double *c0 = nullptr;
   int32_t *comp_tup = nullptr;
   int64_t tab_entries = 0;
@@ -139,11 +141,28 @@ int make_model(int32_t d, int32_t m, const double *c0, const std::vector<HostCom
 
 int set_device_of(const hdmr_model *model);
 
-// Cell-sorted FP64 evaluation (eval_sorted.hip).
-int eval_sorted_fp64(const hdmr_model *model, const double *X, int64_t n, double *F, hipStream_t stream);
+// Cell-sorted evaluation (eval_sorted.hip), precision HDMR_PLAIN_FP64 or
+// HDMR_MIXED.
+int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, int precision,
+                hipStream_t stream);
 
 // Plan the sorted-evaluation passes of a model and upload the pass tuples.
 int plan_passes(hdmr_model *M);
+
+// Device timing of evaluation stages (timing.hip).
+enum TimedStage : int { STAGE_SORT = 0, STAGE_ROWS = 1, STAGE_CONTRACT = 2, STAGE_COUNT = 3 };
+bool timing_on();
+// Records a start event on construction and a stop event on destruction
+// when timing is enabled; does nothing otherwise.
+struct StageTimer {
+  StageTimer(int stage, hipStream_t s);
+  ~StageTimer();
+  StageTimer(const StageTimer &) = delete;
+  StageTimer &operator=(const StageTimer &) = delete;
+  int stage;
+  hipStream_t stream;
+  void *start = nullptr;
+};
 
 }  // namespace hdmr
 

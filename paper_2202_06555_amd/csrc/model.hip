@@ -52,6 +52,7 @@ void free_device(hdmr_model *M) {
   (void)hipFree(M->tups);
   (void)hipFree(M->tab);
   (void)hipFree(M->alpha);
+  (void)hipFree(M->alpha32);
   (void)hipFree(M->c0);
   (void)hipFree(M->comp_tup);
   (void)hipFree(M->pass_tups);
@@ -59,11 +60,17 @@ void free_device(hdmr_model *M) {
   M->tups = nullptr;
   M->tab = nullptr;
   M->alpha = nullptr;
+  M->alpha32 = nullptr;
   M->c0 = nullptr;
   M->comp_tup = nullptr;
 }
 
 }  // namespace
+
+__global__ void k_to_f32(float *__restrict__ dst, const double *__restrict__ src, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
 
 __global__ void k_gather_rows(double *__restrict__ dst, const double *__restrict__ src, const int64_t *__restrict__ map,
                               int64_t nrows, int32_t m, int32_t ms, int32_t stride, int32_t col) {
@@ -267,6 +274,22 @@ int make_model(int32_t d, int32_t m, const double *c0, const std::vector<HostCom
       return rc;
     }
   }
+  {
+    // FP32 surpluses for the mixed-precision path (same row order and stride)
+    const int64_t count = std::max<int64_t>(total * ms, 1);
+    hipError_t e = hipMalloc((void **)&M->alpha32, (size_t)count * sizeof(float));
+    if (e == hipSuccess) {
+      M->device_bytes += count * (int64_t)sizeof(float);
+      hipLaunchKernelGGL(k_to_f32, dim3((unsigned)std::min<int64_t>((count + 255) / 256, 65536)), dim3(256), 0,
+                         (hipStream_t)0, M->alpha32, M->alpha, total * ms);
+      e = hipDeviceSynchronize();
+    }
+    if (e != hipSuccess) {
+      free_device(M);
+      delete M;
+      return hip_fail(e, "FP32 surpluses");
+    }
+  }
   if ((rc = plan_passes(M))) {
     free_device(M);
     delete M;
@@ -344,6 +367,26 @@ int plan_passes(hdmr_model *M) {
       shift += P.cell_lv[q];
     }
     P.key_bits = shift;
+    // (cell, row) incidences over all cells: along one key dimension a row of
+    // level l <= c covers 2^(c - l + 1) of the 2^c cells, a finer row one;
+    // a key dimension the tuple lacks contributes all its 2^c cells
+    P.list_bound = 0;
+    for (int j = P.tup_begin; j < P.tup_end; ++j) {
+      const PassTup &pt = M->pass_tups_h[j];
+      const TupDesc &T = M->tups_h[pt.tup];
+      const Component &c = M->comps[T.comp];
+      const int64_t next = pt.tup + 1 < c.tup_end ? (int64_t)M->tups_h[pt.tup + 1].row_base : c.row_end;
+      int64_t cover = next - T.row_base;
+      bool has[KMAX] = {false, false, false, false};
+      for (int q = 0; q < T.k; ++q) {
+        const int pos = pt.pos[q], l = T.lv[q], cl = P.cell_lv[pos];
+        has[pos] = true;
+        if (l <= cl) cover <<= (cl - l + 1);
+      }
+      for (int q = 0; q < P.k; ++q)
+        if (!has[q]) cover <<= P.cell_lv[q];
+      P.list_bound += cover;
+    }
   }
   int64_t scratch = 0;
   (void)hipFree(M->pass_tups);
@@ -407,6 +450,9 @@ int hdmr_get_info(const hdmr_model *model, hdmr_model_info *info) {
   info->device_bytes = model->device_bytes;
   info->max_level = model->max_level;
   info->max_k = model->max_k;
+  info->n_passes = (int32_t)model->passes.size();
+  info->pass_key_dims = 0;
+  for (const Pass &P : model->passes) info->pass_key_dims += P.k;
   return HDMR_OK;
 }
 

@@ -30,6 +30,7 @@ MIXED = 1
 EXPORTS = (
     "hdmr_init", "asg_build_components", "hdmr_model_from_surpluses", "hdmr_eval", "hdmr_eval_grad",
     "hdmr_get_info", "hdmr_export_component", "hdmr_free", "hdmr_last_error", "hdmr_eval_stats",
+    "hdmr_timing_enable", "hdmr_timing_read",
 )
 
 _LOCK = threading.Lock()
@@ -53,7 +54,8 @@ class _BuildParams(ctypes.Structure):
 class _Info(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("m", ctypes.c_int32), ("n_components", ctypes.c_int32),
                 ("n_tuples", ctypes.c_int32), ("n_rows", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("max_level", ctypes.c_int32), ("max_k", ctypes.c_int32)]
+                ("max_level", ctypes.c_int32), ("max_k", ctypes.c_int32), ("n_passes", ctypes.c_int32),
+                ("pass_key_dims", ctypes.c_int32)]
 
 
 CALLBACK_T = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
@@ -78,6 +80,8 @@ def lib():
                 "hdmr_get_info": [vp, vp],
                 "hdmr_eval_stats": [vp, vp, i64, vp, vp, vp],
                 "hdmr_export_component": [vp, i32, vp, vp, vp, vp, vp, vp, vp],
+                "hdmr_timing_enable": [i32],
+                "hdmr_timing_read": [ctypes.c_char_p, vp, vp],
             }
             for name, args in sig.items():
                 fn = getattr(L, name)
@@ -240,6 +244,18 @@ def hdmr_eval_stats(model: Model, points, stream=None):
     _check(lib().hdmr_eval_stats(model.handle, _dev(points, "points", (n, inf["d"])), n, ctypes.byref(h),
                                  ctypes.byref(p), _stream_ptr(stream)))
     return h.value, p.value
+
+
+def hdmr_timing_enable(on: bool = True):
+    """Start (and reset) or stop the device timing of evaluation stages."""
+    _check(lib().hdmr_timing_enable(1 if on else 0))
+
+
+def hdmr_timing_read(stage: str):
+    """(total_ms, launches) of a stage ('sort', 'rows', 'contract') since enabling."""
+    t, c = ctypes.c_double(), ctypes.c_int64()
+    _check(lib().hdmr_timing_read(stage.encode(), ctypes.byref(t), ctypes.byref(c)))
+    return t.value, c.value
 
 
 def hdmr_get_info(model: Model):

@@ -50,3 +50,13 @@ def test_host_validation_errors():
         hd.hdmr_model_from_surpluses(big)
     assert e.value.code == hd.hdmr.HDMR_EUNSUPPORTED
     assert hd.hdmr_last_error() != ""
+
+
+def test_timing_switch_without_device():
+    import paper_2202_06555_amd as hd
+    hd.hdmr_timing_enable(True)
+    assert hd.hdmr_timing_read("contract") == (0.0, 0)
+    with pytest.raises(hd.HdmrError) as e:
+        hd.hdmr_timing_read("nope")
+    assert e.value.code == hd.hdmr.HDMR_EINVAL
+    hd.hdmr_timing_enable(False)

@@ -2,7 +2,8 @@
 test function, same parameters): identical grid point sets (bit-exact, they
 are integer data), surpluses within 1e-12, identical weights and c0; and the
 full-size metric workload (d=100, m=51, 4e6 points) evaluated in the
-benchmark's launch configuration, checked on sampled outputs."""
+benchmark's launch configuration (plain and mixed precision), checked on
+sampled outputs."""
 import numpy as np
 import pytest
 
@@ -139,3 +140,10 @@ def test_c3_full_size_build_and_eval(hd):
     err = float(np.abs(Y.cpu().numpy()[idx] - ref).max())
     print("c3: %d rows, surplus diff %.3e, sampled eval max |err| %.3e" % (hd.hdmr_get_info(gm)["n_rows"], w, err))
     assert err <= TOL
+    # the mixed-precision path on the same launch configuration: normwise 1e-6
+    Ym = hd.hdmr_eval(gm, Xd, precision=hd.MIXED)
+    torch.cuda.synchronize()
+    Ym = Ym.cpu().numpy()[idx]
+    nw = float(np.linalg.norm(Ym - ref) / np.linalg.norm(ref))
+    print("c3 mixed: sampled normwise error %.3e" % nw)
+    assert nw <= 1e-6

@@ -1,7 +1,11 @@
 """GPU parity of hdmr_eval / hdmr_eval_grad (plain FP64 path) against the FP64
 oracle on the same seeded inputs, through the C ABI.  Bar: max |GPU - oracle|
 <= 1e-12 on values; gradients (slopes up to 2^L) at 1e-12 relative to the
-magnitude of the summed terms."""
+magnitude of the summed terms.  Every case runs on both evaluation kernels:
+the point-per-wavefront gather kernel and the cell-sorted matrix-core path
+(selected through HDMR_EVAL_PATH)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -21,6 +25,17 @@ def hd():
     import paper_2202_06555_amd as hd
     hd.hdmr_init(0)
     return hd
+
+
+@pytest.fixture(autouse=True, params=["gather", "sorted"])
+def eval_path(request):
+    old = os.environ.get("HDMR_EVAL_PATH")
+    os.environ["HDMR_EVAL_PATH"] = request.param
+    yield request.param
+    if old is None:
+        os.environ.pop("HDMR_EVAL_PATH", None)
+    else:
+        os.environ["HDMR_EVAL_PATH"] = old
 
 
 def _dev(X):
