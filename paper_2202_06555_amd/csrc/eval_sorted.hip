@@ -9,14 +9,16 @@
 // dimensions):
 //   keys     : the cell of every point in the key dimensions (<= 16 bits);
 //   sort     : radix sort of (key, point) pairs, so the points of a cell are
-//              neighbours; cell bounds; tiles of <= 64 points of one cell;
+//              neighbours; cell bounds;
 //   rows     : the rows of every nonempty cell through the directory
-//              (count, exclusive scan, write: a CSR of (cell, row));
-//   contract : a workgroup per tile stages the tile's rows, the basis weights
-//              W = w_S prod phi (eq (3.1), eq (3.2)) and the surplus rows in
-//              LDS and multiplies them on the matrix cores; the per-point
-//              sums are added to the FP64 output rows (the first pass writes
-//              c0 + sum).
+//              (count, exclusive scan, write: a CSR of (cell, row)); work
+//              items of <= 256 points of one cell;
+//   contract : a workgroup per work item stages the cell's rows and the
+//              surplus operands once, then per 64-point sub-tile forms the
+//              basis weights W = w_S prod phi (eq (3.1), eq (3.2)) in LDS and
+//              multiplies W by the surplus rows on the matrix cores; the
+//              per-point sums are added to the FP64 output rows, which start
+//              at c0.
 // Plain: FP64 weights and surpluses, FP64 MFMA, FP64 accumulation.  Mixed:
 // FP32 weights and surpluses split into three BF16 terms, BF16 MFMA with FP32
 // accumulation per pass, FP64 accumulation across passes and of c0.
@@ -33,6 +35,24 @@
 namespace hdmr {
 
 namespace {
+
+constexpr int TPTS = 64;  // points per sub-tile (one MFMA row group per 16)
+#ifndef HDMR_TR_FP64
+#define HDMR_TR_FP64 48
+#endif
+#ifndef HDMR_CHUNK
+#define HDMR_CHUNK 256
+#endif
+#ifndef HDMR_TR_MIXED
+#define HDMR_TR_MIXED 64
+#endif
+#ifndef HDMR_TILE_GRID
+#define HDMR_TILE_GRID 4096
+#endif
+constexpr int TR_FP64 = HDMR_TR_FP64;    // rows per batch, FP64 contraction
+constexpr int TR_MIXED = HDMR_TR_MIXED;  // rows per batch, mixed contraction
+constexpr int TILE_GRID = HDMR_TILE_GRID;  // workgroups of a contraction launch
+constexpr int CHUNK = HDMR_CHUNK;          // points per work item (<= 4 sub-tiles)
 
 __global__ void k_transpose(const double *__restrict__ X, int64_t n, int d, double *__restrict__ XT,
                             uint8_t *__restrict__ nanflag) {
@@ -112,11 +132,11 @@ __global__ void k_bounds(const uint16_t *__restrict__ ks, int64_t n, uint32_t *_
 __global__ void k_tile_counts(const uint32_t *__restrict__ start, const uint32_t *__restrict__ end, int nbins,
                               uint32_t *__restrict__ ntile) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < nbins) ntile[b] = (end[b] - start[b] + WAVE - 1) / WAVE;
+  if (b < nbins) ntile[b] = (end[b] - start[b] + CHUNK - 1) / CHUNK;
 }
 
-// Tiles of <= 64 consecutive sorted points of one cell: (first sorted point,
-// count, rows of the cell, first CSR entry of the cell).
+// Work items of <= CHUNK consecutive sorted points of one cell: (first sorted
+// point, count, rows of the cell, first CSR entry of the cell).
 __global__ void k_write_tiles(const uint32_t *__restrict__ start, const uint32_t *__restrict__ end,
                               const uint32_t *__restrict__ ntile, const uint32_t *__restrict__ toff,
                               const uint32_t *__restrict__ crows, const uint32_t *__restrict__ coff, int nbins,
@@ -125,7 +145,7 @@ __global__ void k_write_tiles(const uint32_t *__restrict__ start, const uint32_t
   if (b >= nbins) return;
   const uint32_t s0 = start[b], cnt = end[b] - start[b];
   for (uint32_t t = 0; t < ntile[b]; ++t)
-    tiles[toff[b] + t] = make_uint4(s0 + t * WAVE, min(cnt - t * WAVE, (uint32_t)WAVE), crows[b], coff[b]);
+    tiles[toff[b] + t] = make_uint4(s0 + t * CHUNK, min(cnt - t * CHUNK, (uint32_t)CHUNK), crows[b], coff[b]);
   if (b == nbins - 1) *ntiles = toff[b] + ntile[b];
 }
 
@@ -267,82 +287,50 @@ __device__ __forceinline__ double row_weight(const CellRow &R, const uint4 &ix, 
   return w;
 }
 
-constexpr int TPTS = 64;  // points per tile (one MFMA row tile per 16)
-#ifndef HDMR_TR_FP64
-#define HDMR_TR_FP64 48
-#endif
-#ifndef HDMR_TR_MIXED
-#define HDMR_TR_MIXED 64
-#endif
-#ifndef HDMR_TILE_GRID
-#define HDMR_TILE_GRID 4096
-#endif
-constexpr int TR_FP64 = HDMR_TR_FP64;    // rows per batch, FP64 contraction
-constexpr int TR_MIXED = HDMR_TR_MIXED;  // rows per batch, mixed contraction
-constexpr int TILE_GRID = HDMR_TILE_GRID;  // workgroups of a contraction launch
 
-// Per-thread staging registers of one tile: thread t < count holds point t
-// (id and key coordinates), thread t < min(rows, TR) holds row t of the cell.
+// A work item of the contraction is a chunk of <= CHUNK consecutive sorted
+// points of one cell (record: first sorted point, count, rows of the cell,
+// first CSR entry of the cell), processed as 64-point sub-tiles that share
+// the cell's staged rows and surplus operands.
+
 // (Scalar and native vector members only: arrays, or HIP's uint4 with its
-// union storage, in a per-thread struct end up in scratch memory.)
+// union storage, in per-thread structs end up in scratch memory.)
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-struct TileRegs {
-  int32_t pid;
-  double x0, x1, x2, x3;
+struct RowRegs {  // thread t < min(rows, TR): row t of a batch
   u32x4 row0, row1;  // the CellRow, as two 16-byte words
   u32x4 ix;
+};
+struct PtRegs {  // thread t < points of a sub-tile: point t
+  int32_t pid;
+  double x0, x1, x2, x3;
 };
 static_assert(sizeof(CellRow) == 32, "CellRow is staged as two 16-byte words");
 
 template <int TR>
-__device__ __forceinline__ void fetch_tile(const uint4 &rec, int t, int k, const int32_t *__restrict__ spid,
-                                           const double *__restrict__ sx, int64_t n,
-                                           const CellRow *__restrict__ list, const uint4 *__restrict__ idx,
-                                           TileRegs &g) {
-  const uint32_t start = rec.x, count = rec.y, R = rec.z, base = rec.w;
-  if ((uint32_t)t < count) {
-    g.pid = spid[start + t];
-    const double *p = sx + start + t;
-    g.x0 = p[0];
-    g.x1 = k > 1 ? p[n] : 0.0;
-    g.x2 = k > 2 ? p[2 * n] : 0.0;
-    g.x3 = k > 3 ? p[3 * n] : 0.0;
-  }
-  if ((uint32_t)t < min(R, (uint32_t)TR)) {
-    const u32x4 *src = reinterpret_cast<const u32x4 *>(list + (int64_t)base + t);
-    g.row0 = src[0];
-    g.row1 = src[1];
-    g.ix = *reinterpret_cast<const u32x4 *>(idx + (int64_t)base + t);
-  }
-}
-
-// Tile record i, or an empty record past the end (a value select: a
-// conditional load would become a load through a selected pointer).
-__device__ __forceinline__ uint4 tile_rec(const uint4 *__restrict__ tiles, int64_t i, int64_t ntiles) {
-  const uint4 v = tiles[i < ntiles ? i : ntiles - 1];
-  const bool in = i < ntiles;
-  return make_uint4(in ? v.x : 0u, in ? v.y : 0u, in ? v.z : 0u, in ? v.w : 0u);
-}
-
-// Tile meta in LDS (double-buffered: the next tile's is written while the
-// current one is contracted).
-template <int TR>
-struct TileMeta {
+struct RowsLds {
   CellRow rows[TR];
   uint4 ix[TR];
+};
+struct PtsLds {
   double xs[TPTS][KMAX];
   int32_t pid[TPTS];
 };
 
 template <int TR>
-__device__ __forceinline__ void store_tile(TileMeta<TR> &S, const TileRegs &g, int t) {
-  if (t < TPTS) {
-    S.pid[t] = g.pid;
-    S.xs[t][0] = g.x0;
-    S.xs[t][1] = g.x1;
-    S.xs[t][2] = g.x2;
-    S.xs[t][3] = g.x3;
+__device__ __forceinline__ void fetch_rows(const uint4 &rec, int bt, int t, const CellRow *__restrict__ list,
+                                           const uint4 *__restrict__ idx, RowRegs &g) {
+  const int R = (int)rec.z;
+  const int64_t e = (int64_t)rec.w + bt * TR + t;
+  if (t < min(TR, R - bt * TR)) {
+    const u32x4 *src = reinterpret_cast<const u32x4 *>(list + e);
+    g.row0 = src[0];
+    g.row1 = src[1];
+    g.ix = *reinterpret_cast<const u32x4 *>(idx + e);
   }
+}
+
+template <int TR>
+__device__ __forceinline__ void store_rows(RowsLds<TR> &S, const RowRegs &g, int t) {
   if (t < TR) {
     u32x4 *dst = reinterpret_cast<u32x4 *>(&S.rows[t]);
     dst[0] = g.row0;
@@ -351,24 +339,88 @@ __device__ __forceinline__ void store_tile(TileMeta<TR> &S, const TileRegs &g, i
   }
 }
 
-// Plain FP64 contraction.  A workgroup of 4 waves takes one tile at a time
-// (grid-stride over the tiles); wave w owns the 16 outputs o0 + 16w ..; the
-// basis weights W (64 points x TR rows of the cell) are formed once in LDS
-// and shared by the waves (MFMA A operand); each wave loads its own surplus
-// slice (B operand) straight into registers.  The next tile's points and
-// first rows are loaded at the start of a tile and parked in the other LDS
-// buffer before the MFMA phase.  The per-point sums go to the FP64 outputs:
-// the first pass writes c0 + sum, later passes add with device atomics (each
-// (point, output) has one writer per pass).
+__device__ __forceinline__ void fetch_pts(const uint4 &rec, int sub, int t, int k, const int32_t *__restrict__ spid,
+                                          const double *__restrict__ sx, int64_t n, PtRegs &g) {
+  const int c = (int)rec.y - sub * TPTS;
+  if (t < min(c, TPTS)) {
+    const int64_t i = (int64_t)rec.x + sub * TPTS + t;
+    g.pid = spid[i];
+    const double *p = sx + i;
+    g.x0 = p[0];
+    g.x1 = k > 1 ? p[n] : 0.0;
+    g.x2 = k > 2 ? p[2 * n] : 0.0;
+    g.x3 = k > 3 ? p[3 * n] : 0.0;
+  }
+}
+
+__device__ __forceinline__ void store_pts(PtsLds &S, const PtRegs &g, int t) {
+  if (t < TPTS) {
+    S.pid[t] = g.pid;
+    S.xs[t][0] = g.x0;
+    S.xs[t][1] = g.x1;
+    S.xs[t][2] = g.x2;
+    S.xs[t][3] = g.x3;
+  }
+}
+
+// Work item i, or an empty record past the end (a value select: a
+// conditional load would become a load through a selected pointer).
+__device__ __forceinline__ uint4 tile_rec(const uint4 *__restrict__ tiles, int64_t i, int64_t ntiles) {
+  const uint4 v = tiles[i < ntiles ? i : ntiles - 1];
+  const bool in = i < ntiles;
+  return make_uint4(in ? v.x : 0u, in ? v.y : 0u, in ? v.z : 0u, in ? v.w : 0u);
+}
+
+// Sequencing shared by the two contraction kernels.  A workgroup of 4 waves
+// walks its items (grid stride); per item, batches of TR rows; per batch,
+// 64-point sub-tiles.  Rows of the next item and points of the next sub-tile
+// are loaded into registers at the start of a step and parked in the second
+// LDS buffer before the step's MFMA phase.  Each step:
+//   sync; [batch start: stage the batch's rows, load the wave's surplus
+//   operands]; form the weights of the sub-tile into LDS; sync; MFMA;
+//   add the sums to the outputs (which start at c0).
+// Wave w owns the 16 outputs o0 + 16 w ...
+
+// Adds a wave's MFMA result for one sub-tile to the outputs: lane value
+// (group mt, register i) belongs to point mt * 16 + r0 + i * rs of the
+// sub-tile and output col.  Plain loads and stores: within a pass each
+// (point, output) has exactly one writer and passes are separate launches in
+// stream order.  Two halves of 8 loads keep the live registers bounded.
+template <typename V>
+__device__ __forceinline__ void add_rows(double *__restrict__ F, const int32_t *pid, int m, int col, int cnt, int r0,
+                                         int rs, const V (&acc)[4]) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    double f[2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int pt = (2 * h + a) * 16 + r0 + i * rs;
+        f[a][i] = pt < cnt ? F[(int64_t)pid[pt] * m + col] : 0.0;
+      }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int pt = (2 * h + a) * 16 + r0 + i * rs;
+        if (pt < cnt) F[(int64_t)pid[pt] * m + col] = f[a][i] + (double)acc[2 * h + a][i];
+      }
+  }
+}
+
+// Plain FP64 contraction: FP64 weights in LDS (MFMA A operand, shared by the
+// waves), FP64 surplus operands (B) in registers, FP64 MFMA 16x16x4.
 template <int TR>
 __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const uint4 *__restrict__ tiles,
                                                       const uint32_t *__restrict__ ntiles_p,
                                                       const CellRow *__restrict__ list, const uint4 *__restrict__ idx,
                                                       const int32_t *__restrict__ spid, const double *__restrict__ sx,
-                                                      int64_t n, double *__restrict__ F, int first, int o0) {
+                                                      int64_t n, double *__restrict__ F, int o0) {
   constexpr int WS = TR + 4;  // W row stride (doubles): spreads A-operand reads over the LDS banks
   __shared__ double s_w[TPTS][WS];
-  __shared__ TileMeta<TR> s_meta[2];
+  __shared__ RowsLds<TR> s_rows[2];
+  __shared__ PtsLds s_pts[2];
   const int t = threadIdx.x, lane = t & (WAVE - 1), wid = t / WAVE;
   const int kk = lane >> 4, jj = lane & 15;
   const int m = M.m;
@@ -376,90 +428,100 @@ __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const
   const bool wave_on = o0 + wid * 16 < m;
   const int64_t ntiles = *ntiles_p;
   if (ntiles == 0) return;
-  int64_t ti = blockIdx.x;
-  uint4 rec = tile_rec(tiles, ti, ntiles);
-  uint4 rec_n = tile_rec(tiles, ti + gridDim.x, ntiles);
+  int64_t it = blockIdx.x;
+  uint4 rec = tile_rec(tiles, it, ntiles);
   {
-    TileRegs g{};
-    fetch_tile<TR>(rec, t, P.k, spid, sx, n, list, idx, g);
-    store_tile<TR>(s_meta[0], g, t);
+    RowRegs rg{};
+    PtRegs pg{};
+    fetch_rows<TR>(rec, 0, t, list, idx, rg);
+    fetch_pts(rec, 0, t, P.k, spid, sx, n, pg);
+    store_rows<TR>(s_rows[0], rg, t);
+    store_pts(s_pts[0], pg, t);
   }
-  int cur = 0;
-  for (; ti < ntiles; ti += gridDim.x) {
+  int rb = 0, pb = 0;
+  for (; it < ntiles; it += gridDim.x) {
+    const uint4 rec_n = tile_rec(tiles, it + gridDim.x, ntiles);
     const int count = (int)rec.y, R = (int)rec.z;
-    const uint32_t base = rec.w;
-    const uint4 rec_nn = tile_rec(tiles, ti + 2 * (int64_t)gridDim.x, ntiles);
-    __syncthreads();  // the previous tile is done with s_w and its meta buffer
-    TileRegs g{};
-    fetch_tile<TR>(rec_n, t, P.k, spid, sx, n, list, idx, g);
-    TileMeta<TR> &S = s_meta[cur];
-    const bool work = !(R == 0 && !first);  // nothing to add otherwise (uniform)
-    v4d acc[4];
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) acc[mt] = v4d{0.0, 0.0, 0.0, 0.0};
-    const int nbat = work ? max(1, (R + TR - 1) / TR) : 0;
+    const int nsub = (count + TPTS - 1) / TPTS;
+    const int nbat = (R + TR - 1) / TR;
+    RowRegs rn{};
+    fetch_rows<TR>(rec_n, 0, t, list, idx, rn);
+    if (nbat == 0) {  // no rows: nothing to add (uniform); move the next item in
+      PtRegs pn{};
+      fetch_pts(rec_n, 0, t, P.k, spid, sx, n, pn);
+      __syncthreads();
+      store_rows<TR>(s_rows[rb ^ 1], rn, t);
+      store_pts(s_pts[pb ^ 1], pn, t);
+      rb ^= 1;
+      pb ^= 1;
+      rec = rec_n;
+      continue;
+    }
+    RowsLds<TR> &SR = s_rows[rb];
+    double b[TR / 4];
     for (int bt = 0; bt < nbat; ++bt) {
       const int Rb = min(TR, R - bt * TR);
       const int Rp = (Rb + 3) & ~3;
-      if (bt > 0) {
-        __syncthreads();  // the previous batch is done with s_w and the rows
-        if (t < Rb) {
-          S.rows[t] = list[(int64_t)base + bt * TR + t];
-          S.ix[t] = idx[(int64_t)base + bt * TR + t];
-        }
-        __syncthreads();
-      }
-      // B operand: rows 4j + kk of the batch, this lane's output column
-      double b[TR / 4];
+      for (int sub = 0; sub < nsub; ++sub) {
+        const bool last = bt == nbat - 1 && sub == nsub - 1;
+        PtRegs pn{};
+        if (sub + 1 < nsub)
+          fetch_pts(rec, sub + 1, t, P.k, spid, sx, n, pn);
+        else if (!last)
+          fetch_pts(rec, 0, t, P.k, spid, sx, n, pn);
+        else
+          fetch_pts(rec_n, 0, t, P.k, spid, sx, n, pn);
+        __syncthreads();  // the previous step is done with s_w, its points and (new batch) the rows
+        if (sub == 0) {
+          if (bt > 0) {
+            RowRegs rg{};
+            fetch_rows<TR>(rec, bt, t, list, idx, rg);
+            store_rows<TR>(SR, rg, t);
+            __syncthreads();
+          }
+          // B operand: rows 4j + kk of the batch, this lane's output column
 #pragma unroll
-      for (int j = 0; j < TR / 4; ++j) {
-        const int r = 4 * j + kk;
-        b[j] = (r < Rb && col < m) ? M.alpha[(int64_t)S.rows[r].row * M.ms + col] : 0.0;
-      }
-      // W: thread (pt = t / 4, group t % 4) forms rows group, group + 4, ...
-      {
-        const int pt = t >> 2, grp = t & 3;
-        const double x0 = S.xs[pt][0], x1 = S.xs[pt][1], x2 = S.xs[pt][2], x3 = S.xs[pt][3];
+          for (int j = 0; j < TR / 4; ++j) {
+            const int r = 4 * j + kk;
+            b[j] = (r < Rb && col < m) ? M.alpha[(int64_t)SR.rows[r].row * M.ms + col] : 0.0;
+          }
+        }
+        const PtsLds &SP = s_pts[pb];
+        const int cnt = min(count - sub * TPTS, TPTS);
+        {
+          // W: thread (pt = t / 4, group t % 4) forms rows group, group + 4, ...
+          const int pt = t >> 2, grp = t & 3;
+          const double x0 = SP.xs[pt][0], x1 = SP.xs[pt][1], x2 = SP.xs[pt][2], x3 = SP.xs[pt][3];
 #pragma unroll 2
-        for (int r = grp; r < Rp; r += 4)
-          s_w[pt][r] = (r < Rb && pt < count) ? row_weight(S.rows[r], S.ix[r], x0, x1, x2, x3) : 0.0;
-      }
-      if (bt == 0) store_tile<TR>(s_meta[cur ^ 1], g, t);
-      __syncthreads();
-      if (wave_on) {
-#pragma unroll
-        for (int j = 0; j < TR / 4; ++j) {
-          if (4 * j < Rp) {
-            // padded points (pt >= count) have zero weights
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
-              acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[mt * 16 + jj][4 * j + kk], b[j], acc[mt], 0, 0, 0);
-            // bound how far A-operand loads are hoisted (register pressure)
-            __builtin_amdgcn_sched_barrier(0);
-          }
+          for (int r = grp; r < Rp; r += 4)
+            s_w[pt][r] = (r < Rb && pt < cnt) ? row_weight(SR.rows[r], SR.ix[r], x0, x1, x2, x3) : 0.0;
         }
+        store_pts(s_pts[pb ^ 1], pn, t);
+        if (last) store_rows<TR>(s_rows[rb ^ 1], rn, t);
+        __syncthreads();
+        v4d acc[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) acc[mt] = v4d{0.0, 0.0, 0.0, 0.0};
+        if (wave_on) {
+#pragma unroll
+          for (int j = 0; j < TR / 4; ++j) {
+            if (4 * j < Rp) {
+              // padded points (pt >= cnt) have zero weights
+#pragma unroll
+              for (int mt = 0; mt < 4; ++mt)
+                acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[mt * 16 + jj][4 * j + kk], b[j], acc[mt], 0, 0, 0);
+              // bound how far A-operand loads are hoisted (register pressure)
+              __builtin_amdgcn_sched_barrier(0);
+            }
+          }
+          // lane holds rows kk + 4 i of each 16-point group, column jj
+          if (col < m) add_rows(F, SP.pid, m, col, cnt, kk, 4, acc);
+        }
+        pb ^= 1;
       }
     }
-    if (!work) store_tile<TR>(s_meta[cur ^ 1], g, t);
-    // lane holds rows kk + 4 i of each 16-point tile, column jj
-    if (work && wave_on && col < m) {
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int pt = mt * 16 + kk + 4 * i;
-          if (pt < count) {
-            double *dst = F + (int64_t)S.pid[pt] * m + col;
-            if (first)
-              *dst = M.c0[col] + acc[mt][i];
-            else
-              atomicAdd(dst, acc[mt][i]);
-          }
-        }
-    }
+    rb ^= 1;
     rec = rec_n;
-    rec_n = rec_nn;
-    cur ^= 1;
   }
 }
 
@@ -472,26 +534,27 @@ __device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &mid, __b
   lo = (__bf16)(r1 - (float)mid);
 }
 
-// Mixed-precision contraction, same tiling as the FP64 kernel: weights are
-// formed in FP64 (exact x 2^l - i) and rounded to FP32, surpluses are the
-// model's FP32 copy; both are split into three BF16 terms and multiplied on
-// BF16 MFMA 16x16x32 with FP32 accumulation, keeping the six products
-// hi*hi, hi*mid, mid*hi, hi*lo, mid*mid, lo*hi (the dropped ones are below
-// 2^-24 relative).  The per-point FP32 sums of the pass are added to the
-// FP64 outputs (c0 and the sum over passes stay FP64).
+// Mixed-precision contraction, same sequencing: weights are formed in FP64
+// (exact x 2^l - i) and rounded to FP32, surpluses are the model's FP32
+// copy; both are split into three BF16 terms and multiplied on BF16 MFMA
+// 16x16x32 with FP32 accumulation, keeping the six products hi*hi, hi*mid,
+// mid*hi, hi*lo, mid*mid, lo*hi (the dropped ones are below 2^-24 relative).
+// The per-point FP32 sums are added to the FP64 outputs (c0 and the sum over
+// passes and batches stay FP64).
 template <int TR>
-__global__ __launch_bounds__(256, 4) void k_tile_mixed(ModelView M, Pass P, const uint4 *__restrict__ tiles,
+__global__ __launch_bounds__(256, 3) void k_tile_mixed(ModelView M, Pass P, const uint4 *__restrict__ tiles,
                                                        const uint32_t *__restrict__ ntiles_p,
                                                        const CellRow *__restrict__ list,
                                                        const uint4 *__restrict__ idx,
                                                        const int32_t *__restrict__ spid,
                                                        const double *__restrict__ sx,
                                                        const float *__restrict__ alpha32, int64_t n,
-                                                       double *__restrict__ F, int first, int o0) {
+                                                       double *__restrict__ F, int o0) {
   static_assert(TR % 32 == 0, "rows per batch: a multiple of the MFMA depth");
   constexpr int WS = TR + 8;  // W row stride (bf16), 16-byte aligned rows
   __shared__ __attribute__((aligned(16))) __bf16 s_w[3][TPTS][WS];
-  __shared__ TileMeta<TR> s_meta[2];
+  __shared__ RowsLds<TR> s_rows[2];
+  __shared__ PtsLds s_pts[2];
   const int t = threadIdx.x, lane = t & (WAVE - 1), wid = t / WAVE;
   const int kg = lane >> 4, jj = lane & 15;
   const int m = M.m;
@@ -499,112 +562,123 @@ __global__ __launch_bounds__(256, 4) void k_tile_mixed(ModelView M, Pass P, cons
   const bool wave_on = o0 + wid * 16 < m;
   const int64_t ntiles = *ntiles_p;
   if (ntiles == 0) return;
-  int64_t ti = blockIdx.x;
-  uint4 rec = tile_rec(tiles, ti, ntiles);
-  uint4 rec_n = tile_rec(tiles, ti + gridDim.x, ntiles);
+  int64_t it = blockIdx.x;
+  uint4 rec = tile_rec(tiles, it, ntiles);
   {
-    TileRegs g{};
-    fetch_tile<TR>(rec, t, P.k, spid, sx, n, list, idx, g);
-    store_tile<TR>(s_meta[0], g, t);
+    RowRegs rg{};
+    PtRegs pg{};
+    fetch_rows<TR>(rec, 0, t, list, idx, rg);
+    fetch_pts(rec, 0, t, P.k, spid, sx, n, pg);
+    store_rows<TR>(s_rows[0], rg, t);
+    store_pts(s_pts[0], pg, t);
   }
-  int cur = 0;
-  for (; ti < ntiles; ti += gridDim.x) {
+  int rb = 0, pb = 0;
+  for (; it < ntiles; it += gridDim.x) {
+    const uint4 rec_n = tile_rec(tiles, it + gridDim.x, ntiles);
     const int count = (int)rec.y, R = (int)rec.z;
-    const uint32_t base = rec.w;
-    const uint4 rec_nn = tile_rec(tiles, ti + 2 * (int64_t)gridDim.x, ntiles);
-    __syncthreads();
-    TileRegs g{};
-    fetch_tile<TR>(rec_n, t, P.k, spid, sx, n, list, idx, g);
-    TileMeta<TR> &S = s_meta[cur];
-    const bool work = !(R == 0 && !first);
-    v4f acc[4];
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) acc[mt] = v4f{0.f, 0.f, 0.f, 0.f};
-    const int nbat = work ? max(1, (R + TR - 1) / TR) : 0;
+    const int nsub = (count + TPTS - 1) / TPTS;
+    const int nbat = (R + TR - 1) / TR;
+    RowRegs rn{};
+    fetch_rows<TR>(rec_n, 0, t, list, idx, rn);
+    if (nbat == 0) {
+      PtRegs pn{};
+      fetch_pts(rec_n, 0, t, P.k, spid, sx, n, pn);
+      __syncthreads();
+      store_rows<TR>(s_rows[rb ^ 1], rn, t);
+      store_pts(s_pts[pb ^ 1], pn, t);
+      rb ^= 1;
+      pb ^= 1;
+      rec = rec_n;
+      continue;
+    }
+    RowsLds<TR> &SR = s_rows[rb];
+    bf16x8 bh[TR / 32], bm[TR / 32], bl[TR / 32];
     for (int bt = 0; bt < nbat; ++bt) {
       const int Rb = min(TR, R - bt * TR);
       const int Rp = (Rb + 31) & ~31;
-      if (bt > 0) {
+      for (int sub = 0; sub < nsub; ++sub) {
+        const bool last = bt == nbat - 1 && sub == nsub - 1;
+        PtRegs pn{};
+        if (sub + 1 < nsub)
+          fetch_pts(rec, sub + 1, t, P.k, spid, sx, n, pn);
+        else if (!last)
+          fetch_pts(rec, 0, t, P.k, spid, sx, n, pn);
+        else
+          fetch_pts(rec_n, 0, t, P.k, spid, sx, n, pn);
         __syncthreads();
-        if (t < Rb) {
-          S.rows[t] = list[(int64_t)base + bt * TR + t];
-          S.ix[t] = idx[(int64_t)base + bt * TR + t];
-        }
-        __syncthreads();
-      }
-      // B operand: rows 32 st + 8 kg + item of the batch, this lane's column
-      bf16x8 bh[TR / 32], bm[TR / 32], bl[TR / 32];
+        if (sub == 0) {
+          if (bt > 0) {
+            RowRegs rg{};
+            fetch_rows<TR>(rec, bt, t, list, idx, rg);
+            store_rows<TR>(SR, rg, t);
+            __syncthreads();
+          }
+          // B operand: rows 32 st + 8 kg + item of the batch, this lane's column
 #pragma unroll
-      for (int st = 0; st < TR / 32; ++st)
+          for (int st = 0; st < TR / 32; ++st)
 #pragma unroll
-        for (int it = 0; it < 8; ++it) {
-          const int r = 32 * st + 8 * kg + it;
-          const float v = (r < Rb && col < m) ? alpha32[(int64_t)S.rows[r].row * M.ms + col] : 0.f;
-          __bf16 h, md, l;
-          split_bf16(v, h, md, l);
-          bh[st][it] = h;
-          bm[st][it] = md;
-          bl[st][it] = l;
+            for (int e = 0; e < 8; ++e) {
+              const int r = 32 * st + 8 * kg + e;
+              const float v = (r < Rb && col < m) ? alpha32[(int64_t)SR.rows[r].row * M.ms + col] : 0.f;
+              __bf16 h, md, l;
+              split_bf16(v, h, md, l);
+              bh[st][e] = h;
+              bm[st][e] = md;
+              bl[st][e] = l;
+            }
         }
-      {
-        const int pt = t >> 2, grp = t & 3;
-        const double x0 = S.xs[pt][0], x1 = S.xs[pt][1], x2 = S.xs[pt][2], x3 = S.xs[pt][3];
+        const PtsLds &SP = s_pts[pb];
+        const int cnt = min(count - sub * TPTS, TPTS);
+        {
+          const int pt = t >> 2, grp = t & 3;
+          const double x0 = SP.xs[pt][0], x1 = SP.xs[pt][1], x2 = SP.xs[pt][2], x3 = SP.xs[pt][3];
 #pragma unroll 2
-        for (int r = grp; r < Rp; r += 4) {
-          const float v = (r < Rb && pt < count) ? (float)row_weight(S.rows[r], S.ix[r], x0, x1, x2, x3) : 0.f;
-          __bf16 h, md, l;
-          split_bf16(v, h, md, l);
-          s_w[0][pt][r] = h;
-          s_w[1][pt][r] = md;
-          s_w[2][pt][r] = l;
+          for (int r = grp; r < Rp; r += 4) {
+            const float v = (r < Rb && pt < cnt) ? (float)row_weight(SR.rows[r], SR.ix[r], x0, x1, x2, x3) : 0.f;
+            __bf16 h, md, l;
+            split_bf16(v, h, md, l);
+            s_w[0][pt][r] = h;
+            s_w[1][pt][r] = md;
+            s_w[2][pt][r] = l;
+          }
         }
-      }
-      if (bt == 0) store_tile<TR>(s_meta[cur ^ 1], g, t);
-      __syncthreads();
-      if (wave_on) {
+        store_pts(s_pts[pb ^ 1], pn, t);
+        if (last) store_rows<TR>(s_rows[rb ^ 1], rn, t);
+        __syncthreads();
+        v4f acc[4];
 #pragma unroll
-        for (int st = 0; st < TR / 32; ++st) {
-          if (32 * st < Rp) {
-            // padded points (pt >= count) have zero weights
+        for (int mt = 0; mt < 4; ++mt) acc[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+        if (wave_on) {
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-              const int ro = mt * 16 + jj, ko = 32 * st + 8 * kg;
-              const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(&s_w[0][ro][ko]);
-              const bf16x8 am = *reinterpret_cast<const bf16x8 *>(&s_w[1][ro][ko]);
-              const bf16x8 al = *reinterpret_cast<const bf16x8 *>(&s_w[2][ro][ko]);
-              v4f c = acc[mt];
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[st], c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[st], c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[st], c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[st], c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm[st], c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[st], c, 0, 0, 0);
-              acc[mt] = c;
+          for (int st = 0; st < TR / 32; ++st) {
+            if (32 * st < Rp) {
+              // padded points (pt >= cnt) have zero weights
+#pragma unroll
+              for (int mt = 0; mt < 4; ++mt) {
+                const int ro = mt * 16 + jj, ko = 32 * st + 8 * kg;
+                const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(&s_w[0][ro][ko]);
+                const bf16x8 am = *reinterpret_cast<const bf16x8 *>(&s_w[1][ro][ko]);
+                const bf16x8 al = *reinterpret_cast<const bf16x8 *>(&s_w[2][ro][ko]);
+                v4f c = acc[mt];
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[st], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[st], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[st], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[st], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm[st], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[st], c, 0, 0, 0);
+                acc[mt] = c;
+                __builtin_amdgcn_sched_barrier(0);
+              }
             }
           }
+          // lane holds rows 4 kg + i of each 16-point group, column jj
+          if (col < m) add_rows(F, SP.pid, m, col, cnt, 4 * kg, 1, acc);
         }
+        pb ^= 1;
       }
     }
-    if (!work) store_tile<TR>(s_meta[cur ^ 1], g, t);
-    // lane holds rows 4 kg + i of each 16-point tile, column jj
-    if (work && wave_on && col < m) {
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int pt = mt * 16 + 4 * kg + i;
-          if (pt < count) {
-            double *dst = F + (int64_t)S.pid[pt] * m + col;
-            if (first)
-              *dst = M.c0[col] + (double)acc[mt][i];
-            else
-              atomicAdd(dst, (double)acc[mt][i]);
-          }
-        }
-    }
+    rb ^= 1;
     rec = rec_n;
-    rec_n = rec_nn;
-    cur ^= 1;
   }
 }
 
@@ -641,7 +715,7 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
           hipSuccess ||
       hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_scan, ntile, toff, 65536, stream) != hipSuccess)
     return fail(HDMR_EDEVICE, "hipcub temporary storage query failed");
-  const size_t max_tiles = (size_t)(n / TPTS) + 65536 + 1;
+  const size_t max_tiles = (size_t)(n / CHUNK) + 65536 + 1;
   const size_t tmp_bytes = std::max(tmp_sort, tmp_scan);
   int rc = HDMR_OK;
   auto release = [&]() {
@@ -666,7 +740,7 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
   hipLaunchKernelGGL(k_fill_u8, dim3(gs), dim3(256), 0, stream, nanflag, n);
   hipLaunchKernelGGL(k_transpose, dim3((unsigned)((n + 31) / 32), (unsigned)((d + 31) / 32)), dim3(256), 0, stream,
                      X, n, d, xt, nanflag);
-  int first = 1;
+  hipLaunchKernelGGL(k_write_c0, dim3(gs), dim3(256), 0, stream, F, M.c0, n, m);
   hipError_t e = hipSuccess;
   for (const Pass &P : model->passes) {
     const int nbins = 1 << P.key_bits;
@@ -705,16 +779,13 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
       for (int o0 = 0; o0 < m; o0 += 64) {
         if (precision == HDMR_PLAIN_FP64)
           hipLaunchKernelGGL(k_tile_fp64<TR_FP64>, dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles, clist,
-                             cidx, spid, sxv, n, F, first, o0);
+                             cidx, spid, sxv, n, F, o0);
         else
           hipLaunchKernelGGL(k_tile_mixed<TR_MIXED>, dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles,
-                             clist, cidx, spid, sxv, (const float *)model->alpha32, n, F, first, o0);
+                             clist, cidx, spid, sxv, (const float *)model->alpha32, n, F, o0);
       }
     }
-    first = 0;
   }
-  if (e == hipSuccess && first)  // no stored rows at all: every output is c0
-    hipLaunchKernelGGL(k_write_c0, dim3(gs), dim3(256), 0, stream, F, M.c0, n, m);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_nan_fix, dim3(gs), dim3(256), 0, stream, F, nanflag, n, m);
     e = hipGetLastError();

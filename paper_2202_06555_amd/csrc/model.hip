@@ -357,12 +357,14 @@ int plan_passes(hdmr_model *M) {
     }
     P.tup_end = (int32_t)M->pass_tups_h.size();
     M->max_pass_tups = std::max(M->max_pass_tups, P.tup_end - P.tup_begin);
-    // cells of a pass: the finest stored level per key dimension, within a
-    // 16-bit key
+    // cells of a pass: one level below the finest stored level per key
+    // dimension (a cell of level c lies inside one support of every level
+    // <= c + 1, so each level multi-index still has one candidate row per
+    // cell), within a 16-bit key
     const int cap = 16 / P.k;
     int shift = 0;
     for (int q = P.k - 1; q >= 0; --q) {
-      P.cell_lv[q] = std::max(1, std::min(lmax[q], cap));
+      P.cell_lv[q] = std::max(1, std::min(lmax[q] - 1, cap));
       P.shift[q] = shift;
       shift += P.cell_lv[q];
     }
