@@ -7,14 +7,14 @@ One step = one hdmr_eval over all points, inputs resident in HBM.  Prints one
 JSON line.  The model is built on the device with asg_build_components from
 the seeded synthetic test function (untimed).  The device time of every
 evaluation stage is taken live with device events on the launch stream
-(hdmr_timing_*); the roofline object prices the dominant stage, the
-matrix-core contraction, by its algorithmic work:
-  flops : 2 per (point, stored row with a nonzero basis product, output);
-  bytes : 8 per (point, output) for the first pass's write, 16 per (point,
-          output) for every later pass's read-modify-write, 8 per stored
-          surplus (FP64; 4 for the mixed path's FP32 copy), 8 per (point,
-          key dimension) of sorted coordinates and 4 per (point, pass) of
-          sorted point ids.
+(hdmr_timing_*); the roofline object prices the dominant kernel, the
+matrix-core contraction (one launch per pass), by its algorithmic work:
+2 flops per (point, stored row with a nonzero basis product, output), against
+the matrix-core peak of its dtype (FP64 for plain, BF16 for mixed).  Also
+reported: the problem-level bytes per launch (outputs, points and model once
+per evaluation), the bytes this design moves (16 per point and output per
+pass for the output read-modify-write), and the HBM traffic measured with
+rocprofv3 FETCH_SIZE + WRITE_SIZE (profiles/, copy-calibrated).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision plain|mixed]
                   [--no-cpu-baseline] [--points N] [--calibrate-copy]
@@ -31,10 +31,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK = 78.6e12      # MI355X FP64 matrix / vector FLOP/s
+FP32_PEAK = 157.3e12     # MI355X FP32 vector FLOP/s
 BF16_PEAK = 2.5e15       # MI355X dense BF16 matrix FLOP/s
 HBM_PEAK = 8.0e12        # MI355X HBM3E bytes/s
 
-KERNEL = {"plain": "k_tile_fp64", "mixed": "k_tile_mixed<3>"}
+KERNEL = {"plain": "k_tile_fp64", "mixed": "k_tile_mixed"}
 
 
 def log(msg):
@@ -50,7 +51,7 @@ def _measured_traffic(kernel, workload):
     """HBM bytes per launch of the contraction kernel from the committed
     counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when
     there is none or the kernel source changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.md" % (kernel.split("<")[0], workload))
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.md" % (kernel, workload))
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -137,37 +138,36 @@ def main():
     launches_per_step = c_launches / args.steps
     per_launch_s = c_ms / 1e3 / c_launches
     P = info["n_passes"]
-    surplus_bytes = 8 if prec == hd.PLAIN_FP64 else 4
-    flops_step = 2.0 * hits * m
-    bytes_step = (n * m * 8.0 * (2 * P - 1) + info["n_rows"] * m * surplus_bytes +
-                  n * (8.0 * info["pass_key_dims"] + 4.0 * P))
-    flops_launch = flops_step / launches_per_step
-    bytes_launch = bytes_step / launches_per_step
+    flops_launch = 2.0 * hits * m / launches_per_step
     mfma_peak = FP64_PEAK if prec == hd.PLAIN_FP64 else BF16_PEAK
-    f_frac = flops_launch / per_launch_s / mfma_peak
-    b_frac = bytes_launch / per_launch_s / HBM_PEAK
+    # problem-level bytes of an evaluation: outputs once, points once, the model once
+    alg_bytes_step = n * m * 8.0 + n * d * 8.0 + info["device_bytes"]
+    # bytes this design must move: every pass re-reads and re-writes the output rows
+    design_bytes_step = (n * m * 16.0 * P + info["n_rows"] * m * (8 if prec == hd.PLAIN_FP64 else 4) +
+                         n * (8.0 * info["pass_key_dims"] + 4.0 * P))
     kern = KERNEL[args.precision]
     traffic = _measured_traffic(kern, args.config)
-    if b_frac >= f_frac:
-        roof = {"bound": "hbm", "achieved": bytes_launch / per_launch_s / 1e9, "peak": HBM_PEAK / 1e9,
-                "unit": "GB/s", "frac": b_frac}
-        other = {"bound": "mfma", "achieved": flops_launch / per_launch_s / 1e12, "peak": mfma_peak / 1e12,
-                 "unit": "TFLOP/s", "frac": f_frac}
-    else:
-        roof = {"bound": "mfma", "achieved": flops_launch / per_launch_s / 1e12, "peak": mfma_peak / 1e12,
-                "unit": "TFLOP/s", "frac": f_frac}
-        other = {"bound": "hbm", "achieved": bytes_launch / per_launch_s / 1e9, "peak": HBM_PEAK / 1e9,
-                 "unit": "GB/s", "frac": b_frac}
-    roof["traffic"] = traffic
-    roof.update({
+    roof = {
+        "bound": "mfma",
+        "achieved": flops_launch / per_launch_s / 1e12,
+        "peak": mfma_peak / 1e12,
+        "unit": "TFLOP/s",
+        "frac": flops_launch / per_launch_s / mfma_peak,
+        "traffic": traffic,
         "kernel": kern,
         "launches_per_step": launches_per_step,
         "avg_launch_ms": per_launch_s * 1e3,
         "algorithmic_flops_per_launch": flops_launch,
-        "algorithmic_bytes_per_launch": bytes_launch,
-        "other_bound": other,
+        "algorithmic_bytes_per_launch": alg_bytes_step / launches_per_step,
+        "design_bytes_per_launch": design_bytes_step / launches_per_step,
+        "hbm_GBps_of_traffic": (traffic / per_launch_s / 1e9) if traffic else None,
+        "hbm_frac_of_traffic": (traffic / per_launch_s / HBM_PEAK) if traffic else None,
         "stage_ms_per_step": {s: v[0] / args.steps for s, v in stages.items()},
-    })
+    }
+    if prec == hd.MIXED:
+        # six BF16 products per useful FMA, and the FP32 vector peak for reference
+        roof["mfma_issued_frac"] = 6.0 * roof["frac"]
+        roof["frac_of_fp32_vector_peak"] = flops_launch / per_launch_s / FP32_PEAK
     out = {
         "metric": "HDMR-ASG point x output evaluations/sec at d=100, m=51",
         "value": value,

@@ -153,6 +153,16 @@ int hdmr_get_info(const hdmr_model *model, hdmr_model_info *info);
 int hdmr_export_component(const hdmr_model *model, int32_t comp, int64_t *npts, int32_t *k, int32_t *dims,
                           uint8_t *levels, uint32_t *indices, double *surpluses, double *weight);
 
+/* Model files.  hdmr_model_save writes d, m, c0 and every component's
+ * index set, weight, grid (levels, odd indices) and surpluses (the model's
+ * internal row order) to a versioned binary file at path; hdmr_model_load
+ * reads one and builds the model on the current device, validating the grids
+ * as hdmr_model_from_surpluses does.  A missing, foreign, truncated or
+ * corrupt file gives HDMR_EINVAL (an unknown version HDMR_EUNSUPPORTED).
+ * Files use the host's byte order. */
+int hdmr_model_save(const hdmr_model *model, const char *path);
+int hdmr_model_load(const char *path, hdmr_model **out);
+
 void hdmr_free(hdmr_model *model);
 
 /* Per-kernel device timing (diagnostic; not part of the method).  While

@@ -30,7 +30,7 @@ MIXED = 1
 EXPORTS = (
     "hdmr_init", "asg_build_components", "hdmr_model_from_surpluses", "hdmr_eval", "hdmr_eval_grad",
     "hdmr_get_info", "hdmr_export_component", "hdmr_free", "hdmr_last_error", "hdmr_eval_stats",
-    "hdmr_timing_enable", "hdmr_timing_read",
+    "hdmr_timing_enable", "hdmr_timing_read", "hdmr_model_save", "hdmr_model_load",
 )
 
 _LOCK = threading.Lock()
@@ -82,6 +82,8 @@ def lib():
                 "hdmr_export_component": [vp, i32, vp, vp, vp, vp, vp, vp, vp],
                 "hdmr_timing_enable": [i32],
                 "hdmr_timing_read": [ctypes.c_char_p, vp, vp],
+                "hdmr_model_save": [vp, ctypes.c_char_p],
+                "hdmr_model_load": [ctypes.c_char_p, vp],
             }
             for name, args in sig.items():
                 fn = getattr(L, name)
@@ -244,6 +246,18 @@ def hdmr_eval_stats(model: Model, points, stream=None):
     _check(lib().hdmr_eval_stats(model.handle, _dev(points, "points", (n, inf["d"])), n, ctypes.byref(h),
                                  ctypes.byref(p), _stream_ptr(stream)))
     return h.value, p.value
+
+
+def hdmr_model_save(model: Model, path: str):
+    """Write the model to a file (see include/hdmr.h for the layout)."""
+    _check(lib().hdmr_model_save(model.handle, os.fsencode(path)))
+
+
+def hdmr_model_load(path: str) -> Model:
+    """Read a model file and build the model on the current device."""
+    h = ctypes.c_void_p()
+    _check(lib().hdmr_model_load(os.fsencode(path), ctypes.byref(h)))
+    return Model(h.value)
 
 
 def hdmr_timing_enable(on: bool = True):

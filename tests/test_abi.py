@@ -60,3 +60,20 @@ def test_timing_switch_without_device():
         hd.hdmr_timing_read("nope")
     assert e.value.code == hd.hdmr.HDMR_EINVAL
     hd.hdmr_timing_enable(False)
+
+
+def test_model_load_rejects_bad_files(tmp_path):
+    import paper_2202_06555_amd as hd
+    with pytest.raises(hd.HdmrError) as e:
+        hd.hdmr_model_load(str(tmp_path / "missing.hdmr"))
+    assert e.value.code == hd.hdmr.HDMR_EINVAL
+    bad = tmp_path / "bad.hdmr"
+    bad.write_bytes(b"not a model file at all")
+    with pytest.raises(hd.HdmrError) as e:
+        hd.hdmr_model_load(str(bad))
+    assert "not a model file" in str(e.value)
+    trunc = tmp_path / "trunc.hdmr"
+    trunc.write_bytes(b"HDMRASG1" + (1).to_bytes(4, "little") + (4).to_bytes(4, "little"))
+    with pytest.raises(hd.HdmrError) as e:
+        hd.hdmr_model_load(str(trunc))
+    assert e.value.code == hd.hdmr.HDMR_EINVAL
