@@ -7,3 +7,4 @@ from .hdmr import (  # noqa: F401
     hdmr_timing_enable,
     hdmr_timing_read, lib,
 )
+from . import surrogate  # noqa: F401,E402

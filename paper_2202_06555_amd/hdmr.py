@@ -31,6 +31,10 @@ EXPORTS = (
     "hdmr_init", "asg_build_components", "hdmr_model_from_surpluses", "hdmr_eval", "hdmr_eval_grad",
     "hdmr_get_info", "hdmr_export_component", "hdmr_free", "hdmr_last_error", "hdmr_eval_stats",
     "hdmr_timing_enable", "hdmr_timing_read", "hdmr_model_save", "hdmr_model_load",
+    # include/hdmr_surrogate.h
+    "mlp_param_count", "mlp_create", "mlp_get_params", "mlp_set_standardization", "mlp_fit_standardization",
+    "mlp_get_standardization", "mlp_forward", "mlp_loss_grads", "mlp_train", "mlp_free", "hdmr_model_select",
+    "mlp_route_create", "mlp_route_info", "mlp_eval_routed", "mlp_route_free",
 )
 
 _LOCK = threading.Lock()
@@ -84,13 +88,27 @@ def lib():
                 "hdmr_timing_read": [ctypes.c_char_p, vp, vp],
                 "hdmr_model_save": [vp, ctypes.c_char_p],
                 "hdmr_model_load": [ctypes.c_char_p, vp],
+                "mlp_param_count": [i32, i32, i32, vp],
+                "mlp_create": [i32, i32, i32, vp, vp],
+                "mlp_get_params": [vp, vp],
+                "mlp_set_standardization": [vp, vp, vp],
+                "mlp_fit_standardization": [vp, vp, i64, vp],
+                "mlp_get_standardization": [vp, vp, vp],
+                "mlp_forward": [vp, vp, i64, vp, vp],
+                "mlp_loss_grads": [vp, vp, vp, vp, i32, vp, vp, vp],
+                "mlp_train": [vp, vp, vp, vp, i64, i32, ctypes.c_float, vp, vp],
+                "hdmr_model_select": [vp, i32, vp, i32, vp, i32, vp],
+                "mlp_route_create": [vp, vp, vp, i64, f64, vp],
+                "mlp_route_info": [vp, vp, vp, vp],
+                "mlp_eval_routed": [vp, vp, i64, vp, i32, vp],
             }
             for name, args in sig.items():
                 fn = getattr(L, name)
                 fn.restype = ctypes.c_int
                 fn.argtypes = args
-            L.hdmr_free.restype = None
-            L.hdmr_free.argtypes = [vp]
+            for name in ("hdmr_free", "mlp_free", "mlp_route_free"):
+                getattr(L, name).restype = None
+                getattr(L, name).argtypes = [vp]
             L.hdmr_last_error.restype = ctypes.c_char_p
             L.hdmr_last_error.argtypes = []
             _LIB = L

@@ -11,10 +11,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _header_functions():
-    txt = open(os.path.join(ROOT, "include", "hdmr.h")).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    names = re.findall(r"^\s*(?:int|void|const char \*)\s*\**\s*(\w+)\s*\(", txt, flags=re.M)
-    return sorted(set(names))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names.update(re.findall(r"^\s*(?:int|void|const char \*)\s*\**\s*(\w+)\s*\(", txt, flags=re.M))
+    return sorted(names)
 
 
 def test_library_exports_header_symbols():
@@ -77,3 +81,14 @@ def test_model_load_rejects_bad_files(tmp_path):
     with pytest.raises(hd.HdmrError) as e:
         hd.hdmr_model_load(str(trunc))
     assert e.value.code == hd.hdmr.HDMR_EINVAL
+
+
+def test_surrogate_host_validation():
+    import paper_2202_06555_amd as hd
+    from paper_2202_06555_amd import surrogate as sg
+    assert sg.mlp_param_count(300, 512, 151) == 300 * 512 + 512 + 2 * (512 * 512 + 512) + 151 * 512 + 151
+    with pytest.raises(hd.HdmrError) as e:
+        sg.mlp_param_count(0, 512, 3)
+    assert e.value.code == hd.hdmr.HDMR_EINVAL
+    with pytest.raises(hd.HdmrError):
+        sg.mlp_create(4, 16, 2, np.zeros(5, np.float32))

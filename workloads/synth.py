@@ -89,14 +89,15 @@ class TestFunction:
     Draw order from ``default_rng(seed)``: c (m), a (m x d), theta (m x d),
     b (m x P), mu (m x P), nu (m x P), kappa (m).  Distributions: c ~ U[0.5,1.5],
     a ~ N(0, 0.5^2), theta ~ U[0, 2 pi], b ~ N(0, 0.3^2), mu, nu ~ U[0,1],
-    kappa ~ U[0.5, 1].  ``pairs`` is the interaction pair set; the kink sits on
-    dimensions (0, 1).  ``ref`` is the reference point of the incremental path
+    kappa ~ U[0.5, 1]; ``pair_scale`` multiplies b and kappa after the draws
+    (order-2 terms smaller than order-1 terms).  ``pairs`` is the interaction
+    pair set; the kink sits on dimensions (0, 1).  ``ref`` is the reference point of the incremental path
     (the anchor of the cut-HDMR builds).
     """
 
     __test__ = False  # not a pytest class
 
-    def __init__(self, d, m, pairs, seed, ref=None, kink=(0, 1)):
+    def __init__(self, d, m, pairs, seed, ref=None, kink=(0, 1), pair_scale=1.0):
         rng = np.random.default_rng(seed)
         self.d, self.m = int(d), int(m)
         self.pairs = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
@@ -108,6 +109,9 @@ class TestFunction:
         self.mu = rng.uniform(0.0, 1.0, size=(m, P))
         self.nu = rng.uniform(0.0, 1.0, size=(m, P))
         self.kappa = rng.uniform(0.5, 1.0, size=m)
+        # optional scale of every order-2 term (pairs and kink), after the draws
+        self.b *= pair_scale
+        self.kappa *= pair_scale
         self.ref = np.full(d, 0.5) if ref is None else np.ascontiguousarray(ref, dtype=np.float64)
         self.kink = tuple(int(k) for k in kink)
         p = _TFParams()
