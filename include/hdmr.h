@@ -125,6 +125,27 @@ int hdmr_eval(const hdmr_model *model, const double *points, int64_t n, double *
 int hdmr_eval_grad(const hdmr_model *model, const double *points, int64_t n, double *values,
                    double *grad, int32_t m, hdmr_stream_t stream);
 
+/* Many models in one call: model i is evaluated at n[i] points
+ * points[i] (dev, n[i] x d_i) into values[i] (dev, n[i] x m_i), as hdmr_eval
+ * does.  Models of uneven size, dimension and output width are batched: every
+ * model routed to the gather kernel runs in one persistent launch (work
+ * units of a few points taken from a device queue, heaviest models first),
+ * replayed from a hipGraph cached per batch signature (models, points,
+ * values, n, precision); models with n >= 16384 are first timed on the call's
+ * data on each candidate path (persistent gather, cell-sorted with two
+ * contraction tile shapes) and the fastest is kept per (model, size bucket
+ * floor(log2 n), precision) -- the call that measures leaves correct values.
+ * Gather-path models compute in FP64 also when precision is HDMR_MIXED.
+ * paths (host, count entries, may be NULL) receives the path used per model:
+ * -1 none (n = 0), 0 persistent gather, 1 cell-sorted, 2 cell-sorted with the
+ * smaller row batch.  All models must live on one device (max d 1900).  The
+ * caller must not free or overwrite a model while a batched call using it
+ * may still run on a stream.  The cached graphs are released when their
+ * models are freed. */
+int hdmr_eval_batched(const hdmr_model *const *models, const double *const *points, const int64_t *n,
+                      double *const *values, int32_t count, int32_t precision, int32_t *paths,
+                      hdmr_stream_t stream);
+
 /* Work counts of an evaluation (diagnostic, synchronous on stream): *hits
  * receives the number of (point, stored row) pairs with a nonzero basis
  * product -- the nonzeros of the sparse basis matrix of eq (3.6) summed over

@@ -51,6 +51,8 @@ constexpr int TPTS = 64;  // points per sub-tile (one MFMA row group per 16)
 #endif
 constexpr int TR_FP64 = HDMR_TR_FP64;    // rows per batch, FP64 contraction
 constexpr int TR_MIXED = HDMR_TR_MIXED;  // rows per batch, mixed contraction
+constexpr int TR_FP64_ALT = 32;          // the alternative row batches an autotuner may pick
+constexpr int TR_MIXED_ALT = 32;
 constexpr int TILE_GRID = HDMR_TILE_GRID;  // workgroups of a contraction launch
 constexpr int CHUNK = HDMR_CHUNK;          // points per work item (<= 4 sub-tiles)
 
@@ -690,8 +692,8 @@ int ws_alloc(T **p, size_t count, hipStream_t s) {
 
 }  // namespace
 
-int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, int precision,
-                hipStream_t stream) {
+int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, int precision, hipStream_t stream,
+                int variant) {
   const ModelView M = model->view();
   const int d = M.d, m = M.m;
   if (n >= (int64_t)INT32_MAX) return fail(HDMR_EUNSUPPORTED, "n >= 2^31 points in one call");
@@ -777,11 +779,17 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
     {
       StageTimer tm(STAGE_CONTRACT, stream);
       for (int o0 = 0; o0 < m; o0 += 64) {
-        if (precision == HDMR_PLAIN_FP64)
+        if (precision == HDMR_PLAIN_FP64 && variant == 0)
           hipLaunchKernelGGL(k_tile_fp64<TR_FP64>, dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles, clist,
                              cidx, spid, sxv, n, F, o0);
-        else
+        else if (precision == HDMR_PLAIN_FP64)
+          hipLaunchKernelGGL(k_tile_fp64<TR_FP64_ALT>, dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles,
+                             clist, cidx, spid, sxv, n, F, o0);
+        else if (variant == 0)
           hipLaunchKernelGGL(k_tile_mixed<TR_MIXED>, dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles,
+                             clist, cidx, spid, sxv, (const float *)model->alpha32, n, F, o0);
+        else
+          hipLaunchKernelGGL(k_tile_mixed<TR_MIXED_ALT>, dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles,
                              clist, cidx, spid, sxv, (const float *)model->alpha32, n, F, o0);
       }
     }

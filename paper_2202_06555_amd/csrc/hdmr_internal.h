@@ -142,9 +142,13 @@ int make_model(int32_t d, int32_t m, const double *c0, const std::vector<HostCom
 int set_device_of(const hdmr_model *model);
 
 // Cell-sorted evaluation (eval_sorted.hip), precision HDMR_PLAIN_FP64 or
-// HDMR_MIXED.
-int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, int precision,
-                hipStream_t stream);
+// HDMR_MIXED; variant 0 uses the default row batch of the contraction, 1 the
+// smaller alternative.
+int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, int precision, hipStream_t stream,
+                int variant = 0);
+
+// Drop every cached batched-launch graph that refers to the model (batched.hip).
+void batched_forget(const hdmr_model *model);
 
 // Plan the sorted-evaluation passes of a model and upload the pass tuples.
 int plan_passes(hdmr_model *M);

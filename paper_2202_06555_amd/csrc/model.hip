@@ -325,6 +325,20 @@ int plan_passes(hdmr_model *M) {
       }
       if (sub) found = (int)p;
     }
+    if (found < 0 && c.k == 1) {
+      // a one-dimensional component outside every pass so far joins a pass of
+      // one other such component (a two-dimensional key), halving their passes
+      for (size_t p = 0; p < M->passes.size() && found < 0; ++p) {
+        Pass &P = M->passes[p];
+        if (P.k != 1 || (int)members[p].size() >= PASS_MAX_COMPS) continue;
+        bool single = true;
+        for (int s2 : members[p]) single &= M->comps[s2].k == 1;
+        if (!single) continue;
+        P.dims[1] = c.dims[0];
+        P.k = 2;
+        found = (int)p;
+      }
+    }
     if (found < 0) {
       Pass P{};
       P.k = c.k;
@@ -490,6 +504,7 @@ void hdmr_free(hdmr_model *model) {
   int cur = -1;
   if (hipGetDevice(&cur) == hipSuccess && cur != model->device) (void)hipSetDevice(model->device);
   (void)hipDeviceSynchronize();
+  batched_forget(model);
   free_device(model);
   if (cur >= 0 && cur != model->device) (void)hipSetDevice(cur);
   delete model;

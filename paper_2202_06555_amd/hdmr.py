@@ -30,7 +30,7 @@ MIXED = 1
 EXPORTS = (
     "hdmr_init", "asg_build_components", "hdmr_model_from_surpluses", "hdmr_eval", "hdmr_eval_grad",
     "hdmr_get_info", "hdmr_export_component", "hdmr_free", "hdmr_last_error", "hdmr_eval_stats",
-    "hdmr_timing_enable", "hdmr_timing_read", "hdmr_model_save", "hdmr_model_load",
+    "hdmr_timing_enable", "hdmr_timing_read", "hdmr_model_save", "hdmr_model_load", "hdmr_eval_batched",
     # include/hdmr_surrogate.h
     "mlp_param_count", "mlp_create", "mlp_get_params", "mlp_set_standardization", "mlp_fit_standardization",
     "mlp_get_standardization", "mlp_forward", "mlp_loss_grads", "mlp_train", "mlp_free", "hdmr_model_select",
@@ -88,6 +88,7 @@ def lib():
                 "hdmr_timing_read": [ctypes.c_char_p, vp, vp],
                 "hdmr_model_save": [vp, ctypes.c_char_p],
                 "hdmr_model_load": [ctypes.c_char_p, vp],
+                "hdmr_eval_batched": [vp, vp, vp, vp, i32, i32, vp, vp],
                 "mlp_param_count": [i32, i32, i32, vp],
                 "mlp_create": [i32, i32, i32, vp, vp],
                 "mlp_get_params": [vp, vp],
@@ -254,6 +255,29 @@ def hdmr_eval_grad(model: Model, points, values=None, grad=None, stream=None):
     _check(lib().hdmr_eval_grad(model.handle, _dev(points, "points", (n, d)), n, _dev(values, "values", (n, m)),
                                 _dev(grad, "grad", (n, d, m)), m, _stream_ptr(stream)))
     return values, grad
+
+
+def hdmr_eval_batched(models, points, values=None, precision=PLAIN_FP64, stream=None):
+    """Evaluate models[i] at points[i] (device tensors) in one batched call.
+    Returns (values list, per-model path array: -1 none, 0 persistent gather,
+    1 cell-sorted, 2 cell-sorted with the smaller row batch)."""
+    import torch
+    k = len(models)
+    if len(points) != k or (values is not None and len(values) != k):
+        raise HdmrError(HDMR_EINVAL, "models, points and values need the same length")
+    infos = [hdmr_get_info(mo) for mo in models]
+    if values is None:
+        values = [torch.empty((p.shape[0], inf["m"]), dtype=torch.float64, device=p.device)
+                  for p, inf in zip(points, infos)]
+    mp = (ctypes.c_void_p * max(k, 1))(*[mo.handle.value for mo in models])
+    pp = (ctypes.c_void_p * max(k, 1))(*[_dev(p, "points", (p.shape[0], inf["d"])).value
+                                         for p, inf in zip(points, infos)])
+    vp_ = (ctypes.c_void_p * max(k, 1))(*[_dev(v, "values", (p.shape[0], inf["m"])).value
+                                          for v, p, inf in zip(values, points, infos)])
+    nn = (ctypes.c_int64 * max(k, 1))(*[p.shape[0] for p in points])
+    paths = np.full(max(k, 1), -1, np.int32)
+    _check(lib().hdmr_eval_batched(mp, pp, nn, vp_, k, int(precision), paths.ctypes.data, _stream_ptr(stream)))
+    return values, paths[:k]
 
 
 def hdmr_eval_stats(model: Model, points, stream=None):

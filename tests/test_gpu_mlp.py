@@ -185,3 +185,61 @@ def test_model_select(env):
     msub["alpha"] = [model["alpha"][s][:, outs] for s in comps]
     got = hd.hdmr_eval(sub, _dev(X)).cpu().numpy()
     np.testing.assert_allclose(got, oracle.evaluate(msub, X), rtol=0, atol=1e-12)
+
+
+def test_surrogate_gain_over_interpolant(env):
+    """What the trained network gains: d=20, m=11, 20 one-dim + 60 two-dim
+    components whose order-2 terms are 100x smaller than the order-1 ones.
+    The network learns the order-2 residual from 2e5 interpolant points; at
+    the tolerance it is validated to (its max-abs error on 5e4 fresh points,
+    every output routed to it) the routed evaluation -- exact order-1 part
+    plus network -- must hold that tolerance on 1e6 other points and run
+    faster than the interpolant alone."""
+    hd, sg = env
+    import time
+    import torch
+    d, m, w = 20, 11, 256
+    cfg = ws.config("c2", d=d, m=m, npairs=60, max_level=6)
+    tf = ws.TestFunction(d, m, cfg["pairs"], 11, ref=cfg["anchor"], pair_scale=0.01)
+    full = hd.asg_build_components(d, m, cfg["anchor"], (tf.c_fn, tf.c_user), comps=cfg["comps"], max_level=6,
+                                   eps_gamma=1e-5)
+    c1 = [s for s, S in enumerate(cfg["comps"]) if len(S) == 1]
+    o1 = sg.hdmr_model_select(full, comps=c1)
+    n, steps, B = 200_000, 6000, 1024
+    X = _dev(ws.points_for(cfg, n=n, seed=1))
+    Yres = hd.hdmr_eval(full, X) - hd.hdmr_eval(o1, X)
+    net = sg.mlp_create(d, w, m, omlp.init_params(d, w, m, seed=0))
+    sg.mlp_fit_standardization(net, Yres)
+    rng = np.random.default_rng(5)
+    order = torch.from_numpy(np.concatenate([rng.permutation(n) for _ in range(steps * B // n + 1)])[:steps * B]
+                             .astype(np.int64)).to("cuda:0")
+    sg.mlp_train(net, X, Yres, order, steps=steps, batch=B, lr0=2e-3, return_losses=False)
+    Xv = _dev(ws.points_for(cfg, n=50_000, seed=3))
+    probe = sg.mlp_route_create(net, full, Xv, 1e30)
+    _, err, _ = sg.mlp_route_info(probe)
+    tau = float(err.max())
+    res_max = float(Yres.abs().max())
+    route = sg.mlp_route_create(net, full, Xv, tau)
+    k, _, _ = sg.mlp_route_info(route)
+    assert k == m
+    assert tau <= 0.5 * res_max, (tau, res_max)      # the network carries most of the order-2 part
+    Xs = _dev(ws.points_for(cfg, n=1_000_000, seed=2))
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return out, float(np.median(ts))
+
+    Yi, t_interp = timed(lambda: hd.hdmr_eval(full, Xs))
+    Yr, t_routed = timed(lambda: sg.mlp_eval_routed(route, Xs))
+    fresh = float((Yr - Yi).abs().max())
+    print("tau %.2e (residual max %.2e), fresh-point max-abs %.2e; interpolant %.2f ms, routed %.2f ms: %.2fx"
+          % (tau, res_max, fresh, t_interp * 1e3, t_routed * 1e3, t_interp / t_routed))
+    assert fresh <= 1.5 * tau
+    assert t_interp / t_routed >= 1.5
