@@ -74,11 +74,22 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device copy first (scale reference for HBM counters)")
+    ap.add_argument("--workload", choices=["eval", "batched", "surrogate"], default="eval",
+                    help="eval: the metric workload (default); batched: many models in one call; "
+                         "surrogate: the learned part on the d=300 workload")
+    ap.add_argument("--models", type=int, default=64, help="batched: number of models")
+    ap.add_argument("--train-points", type=int, default=2_000_000, help="surrogate: interpolant training pairs")
+    ap.add_argument("--epochs", type=int, default=3, help="surrogate: passes over the training pairs")
+    ap.add_argument("--serve-points", type=int, default=2_000_000, help="surrogate: points served")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the evaluation shards by points with no exchange, "
               "so --gpus N > 1 is not run here", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "surrogate":
+        return bench_surrogate(args)
 
     import torch
 
@@ -197,6 +208,125 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample, ws)
         out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    print(json.dumps(out), flush=True)
+
+
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    ev0.record(stream)
+    for _ in range(steps):
+        fn()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps / 1e3
+
+
+def bench_batched(args):
+    """Many independent models of uneven shape in one hdmr_eval_batched call
+    (persistent multi-model launch replayed from a graph; measured path choice)."""
+    import numpy as np
+    import torch
+
+    import paper_2202_06555_amd as hd
+    import workloads.synth as ws
+
+    hd.hdmr_init(0)
+    t0 = time.time()
+    models, points = ws.batched_models(count=args.models, seed=0)
+    gms = [hd.hdmr_model_from_surpluses(mo) for mo in models]
+    X = [torch.from_numpy(P).to("cuda:0") for P in points]
+    Y = [torch.empty((P.shape[0], mo["m"]), dtype=torch.float64, device="cuda:0") for P, mo in zip(points, models)]
+    rows = sum(hd.hdmr_get_info(g)["n_rows"] for g in gms)
+    log("batched: %d models, %d rows, %d points, set up in %.1f s" %
+        (len(gms), rows, sum(P.shape[0] for P in points), time.time() - t0))
+    hits = sum(hd.hdmr_eval_stats(g, x)[0] * mo["m"] for g, x, mo in zip(gms, X, models))
+    _, paths = hd.hdmr_eval_batched(gms, X, Y)          # first call: path measurement
+    t = _timed(lambda: hd.hdmr_eval_batched(gms, X, Y), args.steps, args.warmup)
+    units = sum(P.shape[0] * mo["m"] for P, mo in zip(points, models))
+    flops = 2.0 * hits
+    out = {
+        "metric": "batched HDMR-ASG point x output evaluations/sec (%d models in one call)" % len(gms),
+        "value": units / t, "unit": "point*outputs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "%d order-2 models, d ~ U{10..30}, m = d/2+1, all one- and two-dim components, "
+                               "regular grids of log-uniform size 50..5000, n ~ logU(1e4, 1e5) uniform points"
+                               % len(gms),
+                   "grid_rows": rows, "paths": {str(k): int((paths == k).sum()) for k in (0, 1, 2)}},
+        "roofline": {"bound": "mfma", "achieved": flops / t / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
+                     "frac": flops / t / FP64_PEAK, "traffic": None, "kernel": "k_eval_batched (persistent)",
+                     "note": "whole call timed; FP64 vector FMA work of the gather kernel"},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_surrogate(args):
+    """The learned part on the d=300 workload: 300 one-dim + 300 two-dim
+    components, L=7, m=151, order-2 terms scaled 1/100 (the paper's observed
+    ratio).  Trains the BF16 network on interpolant pairs, validates each
+    output on 1e5 fresh points, routes at max-abs 1e-4, and times network,
+    interpolant and routed evaluation."""
+    import numpy as np
+    import torch
+
+    import paper_2202_06555_amd as hd
+    from paper_2202_06555_amd import surrogate as sg
+    import workloads.synth as ws
+
+    hd.hdmr_init(0)
+    cfg = ws.config("c5")
+    tf = ws.TestFunction(cfg["d"], cfg["m"], cfg["pairs"], cfg["seed"], ref=cfg["anchor"], pair_scale=0.01)
+    full = hd.asg_build_components(cfg["d"], cfg["m"], cfg["anchor"], (tf.c_fn, tf.c_user), comps=cfg["comps"],
+                                   max_level=cfg["max_level"], eps_gamma=cfg["eps_gamma"])
+    c1 = [s for s, S in enumerate(cfg["comps"]) if len(S) == 1]
+    o1 = sg.hdmr_model_select(full, comps=c1)
+    d, m, w = cfg["d"], cfg["m"], 512
+    ntr = args.train_points
+    Xtr = torch.from_numpy(ws.points_for(cfg, n=ntr, seed=1)).to("cuda:0")
+    Ytr = hd.hdmr_eval(full, Xtr) - hd.hdmr_eval(o1, Xtr)
+    net = sg.mlp_create(d, w, m, ws.mlp_init_params(d, w, m, seed=0))
+    sg.mlp_fit_standardization(net, Ytr)
+    B = 4096
+    steps = max(1, args.epochs * ntr // B)
+    rng = np.random.default_rng(5)
+    order = np.concatenate([rng.permutation(ntr) for _ in range(args.epochs + 1)])[:steps * B]
+    order = torch.from_numpy(order.astype(np.int64)).to("cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = sg.mlp_train(net, Xtr, Ytr, order, steps=steps, batch=B, lr0=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del Xtr, Ytr, order
+    Xv = torch.from_numpy(ws.points_for(cfg, n=100_000, seed=3)).to("cuda:0")
+    route = sg.mlp_route_create(net, full, Xv, 1e-4)
+    k, err, use = sg.mlp_route_info(route)
+    Xs = torch.from_numpy(ws.points_for(cfg, n=args.serve_points, seed=2)).to("cuda:0")
+    ns = Xs.shape[0]
+    t_mlp = _timed(lambda: sg.mlp_forward(net, Xs), args.steps, 1)
+    t_int = _timed(lambda: hd.hdmr_eval(full, Xs), args.steps, 1)
+    t_rt = _timed(lambda: sg.mlp_eval_routed(route, Xs), args.steps, 1)
+    flops_fwd = 2.0 * (d * w + 2 * w * w + w * m) * ns
+    out = {
+        "metric": "surrogate-routed point x output evaluations/sec at d=300, m=151 (fallback at max-abs 1e-4)",
+        "value": ns * m / t_rt, "unit": "point*outputs/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": t_rt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 mfma / f32 accumulate (network); f64 (interpolant)", "data": "synthetic",
+        "config": {"workload": "d=300, 300 one-dim + 300 two-dim components (order-2 terms x0.01), L=7, "
+                               "eps_gamma=1e-4, m=151; width-512 4-layer GELU network trained on %d interpolant "
+                               "pairs (%d epochs, batch 4096); %d served points" % (ntr, args.epochs, ns),
+                   "outputs_on_network": int(k), "validated_max_abs_err": {"min": float(err.min()),
+                   "median": float(np.median(err)), "max": float(err.max())},
+                   "train_s": t_train, "loss_first": float(losses[:50].mean()), "loss_last": float(losses[-50:].mean()),
+                   "network_only_evals_per_s": ns * m / t_mlp, "interpolant_evals_per_s": ns * m / t_int},
+        "roofline": {"bound": "mfma", "achieved": flops_fwd / t_mlp / 1e12, "peak": BF16_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": flops_fwd / t_mlp / BF16_PEAK, "traffic": None,
+                     "kernel": "k_gemm (network forward)"},
+    }
     print(json.dumps(out), flush=True)
 
 

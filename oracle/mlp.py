@@ -49,20 +49,6 @@ def gelu_grad(z):
     return 0.5 * (1.0 + _erf(z / SQRT2)) + z * INV_SQRT_2PI * np.exp(-0.5 * z * z)
 
 
-def init_params(d, width, m, seed):
-    """Packed FP32 parameters [W0, b0, W1, b1, W2, b2, W3, b3], W_l (out x in)
-    row-major, W ~ U(-1/sqrt(in), 1/sqrt(in)) and b = 0, drawn from
-    default_rng(seed) in layer order."""
-    rng = np.random.default_rng(seed)
-    dims = [d, width, width, width, m]
-    parts = []
-    for l in range(4):
-        a = 1.0 / math.sqrt(dims[l])
-        parts.append(rng.uniform(-a, a, size=(dims[l + 1], dims[l])).astype(np.float32).ravel())
-        parts.append(np.zeros(dims[l + 1], np.float32))
-    return np.concatenate(parts)
-
-
 def unpack(params, d, width, m):
     dims = [d, width, width, width, m]
     out, o = [], 0

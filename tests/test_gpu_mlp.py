@@ -41,7 +41,7 @@ def _dev(a, dtype=None):
 
 
 def _net(sg, d, w, m, seed, mean=None, std=None):
-    p = omlp.init_params(d, w, m, seed)
+    p = ws.mlp_init_params(d, w, m, seed)
     rng = np.random.default_rng(seed + 100)
     p = p + rng.normal(0, 0.02, size=p.shape).astype(np.float32)   # non-zero biases
     net = sg.mlp_create(d, w, m, p)
@@ -132,7 +132,7 @@ def test_training_and_routing(env):
     c1 = [s for s, S in enumerate(model["comps"]) if len(S) == 1]
     o1 = sg.hdmr_model_select(full, comps=c1)
     Yres = hd.hdmr_eval(full, X) - hd.hdmr_eval(o1, X)
-    net = sg.mlp_create(d, w, m, omlp.init_params(d, w, m, seed=3))
+    net = sg.mlp_create(d, w, m, ws.mlp_init_params(d, w, m, seed=3))
     sg.mlp_fit_standardization(net, Yres)
     steps, B = 400, 256
     order = torch.from_numpy(np.concatenate([rng.permutation(n) for _ in range(steps * B // n + 1)])[:steps * B]
@@ -208,7 +208,7 @@ def test_surrogate_gain_over_interpolant(env):
     n, steps, B = 200_000, 6000, 1024
     X = _dev(ws.points_for(cfg, n=n, seed=1))
     Yres = hd.hdmr_eval(full, X) - hd.hdmr_eval(o1, X)
-    net = sg.mlp_create(d, w, m, omlp.init_params(d, w, m, seed=0))
+    net = sg.mlp_create(d, w, m, ws.mlp_init_params(d, w, m, seed=0))
     sg.mlp_fit_standardization(net, Yres)
     rng = np.random.default_rng(5)
     order = torch.from_numpy(np.concatenate([rng.permutation(n) for _ in range(steps * B // n + 1)])[:steps * B]

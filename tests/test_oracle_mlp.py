@@ -7,6 +7,7 @@ import math
 import numpy as np
 
 from oracle import mlp
+import workloads.synth as ws
 
 
 def test_bf16_rounding_bit_patterns():
@@ -40,7 +41,7 @@ def test_gelu_values_and_slope():
 def test_gradients_match_finite_differences():
     d, w, m, B = 5, 7, 3, 4
     rng = np.random.default_rng(0)
-    p = mlp.init_params(d, w, m, seed=1).astype(np.float64)
+    p = ws.mlp_init_params(d, w, m, seed=1).astype(np.float64)
     p += rng.normal(0, 0.1, size=p.shape)           # non-zero biases too
     X = rng.random((B, d))
     Y = rng.normal(size=(B, m))
@@ -81,7 +82,7 @@ def test_cosine_schedule_end_points():
 
 def test_bf16_storage_is_close_to_exact():
     d, w, m = 6, 16, 4
-    p = mlp.init_params(d, w, m, seed=2).astype(np.float64)
+    p = ws.mlp_init_params(d, w, m, seed=2).astype(np.float64)
     X = np.random.default_rng(3).random((10, d))
     a, _ = mlp.forward(p, X, d, w, m, storage="exact")
     b, _ = mlp.forward(p, X, d, w, m, storage="bf16")

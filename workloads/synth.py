@@ -245,6 +245,71 @@ def synthetic_regular_model(d, m, order, ell, seed):
             "levels": levels, "indices": indices, "alpha": alpha}
 
 
+def mlp_init_params(d, width, m, seed):
+    """Initial parameters of the surrogate network, packed [W0, b0, ..., W3, b3]
+    in FP32 with W_l (out x in) row-major: W ~ U(-1/sqrt(in), 1/sqrt(in)) drawn
+    from default_rng(seed) in layer order, biases zero."""
+    rng = np.random.default_rng(seed)
+    dims = [d, width, width, width, m]
+    parts = []
+    for l in range(4):
+        a = 1.0 / np.sqrt(dims[l])
+        parts.append(rng.uniform(-a, a, size=(dims[l + 1], dims[l])).astype(np.float32).ravel())
+        parts.append(np.zeros(dims[l + 1], np.float32))
+    return np.concatenate(parts)
+
+
+_REGULAR_CACHE = {}
+
+
+def _regular_cached(k, ell):
+    key = (k, ell)
+    if key not in _REGULAR_CACHE:
+        _REGULAR_CACHE[key] = regular_levels(k, ell)
+    return _REGULAR_CACHE[key]
+
+
+def regular_grid_size(k, ell):
+    """Points of a k-dimensional regular sparse grid of level ell."""
+    return _regular_cached(k, ell)[0].shape[0]
+
+
+def batched_models(count=64, seed=0, d_range=(10, 30), size_range=(50, 5000), n_range=(10_000, 100_000),
+                   max_ell=10):
+    """A batch of independent order-2 models of uneven shape (the batched
+    workload).  Model i draws from default_rng(seed + i): d ~ U{d_range},
+    m = d // 2 + 1, c0 ~ N(0,1)^m, then per component (all d one-dimensional
+    and all C(d,2) two-dimensional index sets, in (|S|, lexicographic) order) a
+    target size N ~ logU(size_range) realised as the smallest regular
+    (downward-closed) sparse grid with at least N points (level <= max_ell),
+    with alpha ~ N(0,1) 2^(-2|l|_1) per grid point; then n ~ logU(n_range)
+    evaluation points uniform on [0,1]^d.  Returns (models, points)."""
+    models, points = [], []
+    for i in range(count):
+        rng = np.random.default_rng(seed + i)
+        d = int(rng.integers(d_range[0], d_range[1] + 1))
+        m = d // 2 + 1
+        c0 = rng.standard_normal(m)
+        comps = all_components(d, 2)
+        levels, indices, alpha = [], [], []
+        for S in comps:
+            k = len(S)
+            target = float(np.exp(rng.uniform(np.log(size_range[0]), np.log(size_range[1]))))
+            ell = 1
+            while ell < max_ell and regular_grid_size(k, ell) < target:
+                ell += 1
+            lv, ix = _regular_cached(k, ell)
+            z = rng.standard_normal((lv.shape[0], m))
+            levels.append(lv)
+            indices.append(ix)
+            alpha.append(z * np.ldexp(1.0, -2 * lv.astype(np.int64).sum(axis=1))[:, None])
+        n = int(np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1]))))
+        models.append({"d": d, "m": m, "c0": c0, "comps": comps, "weights": np.ones(len(comps)),
+                       "levels": levels, "indices": indices, "alpha": alpha})
+        points.append(rng.random((n, d)))
+    return models, points
+
+
 # --------------------------------------------------------------------------
 # named workload configurations
 # --------------------------------------------------------------------------
