@@ -87,12 +87,17 @@ __global__ __launch_bounds__(256) void k_eval_batched(const BatchItem *__restric
       wave_sync();
       const bool is_nan = ballot(nan_here) != 0;
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      // the level multi-index descriptors do not depend on the point: the
+      // next group's are loaded while the current group is processed
+      TupDesc Tn{};
+      if (lane < M.ntup) Tn = M.tups[lane];
       for (int t0 = 0; t0 < M.ntup; t0 += WAVE) {
         const int t = t0 + lane;
+        const TupDesc T = Tn;
+        if (t + WAVE < M.ntup) Tn = M.tups[t + WAVE];
         int32_t row = -1;
         double w = 0.0;
         if (t < M.ntup) {
-          const TupDesc T = M.tups[t];
           w = T.w;
           uint32_t slot = 0;
 #pragma unroll
@@ -116,7 +121,25 @@ __global__ __launch_bounds__(256) void k_eval_batched(const BatchItem *__restric
           qw[pos] = w;
         }
         wave_sync();
-        for (int h = sub; h < cnt; h += HPI) {
+        int h = sub;
+        if (opl == 1) {
+          // four hits in flight per step
+          const bool on = ol < m;
+          for (; h + 3 * HPI < cnt; h += 4 * HPI) {
+            int32_t r[4];
+            double ww[4], a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              r[u] = qrow[h + u * HPI];
+              ww[u] = qw[h + u * HPI];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] = on ? M.alpha[(int64_t)r[u] * M.ms + ol] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[0] = fma(ww[u], a[u], acc[0]);
+          }
+        }
+        for (; h < cnt; h += HPI) {
           const int32_t r = qrow[h];
           const double ww = qw[h];
 #pragma unroll
