@@ -74,9 +74,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device copy first (scale reference for HBM counters)")
-    ap.add_argument("--workload", choices=["eval", "batched", "surrogate"], default="eval",
+    ap.add_argument("--workload", choices=["eval", "batched", "surrogate", "grad"], default="eval",
                     help="eval: the metric workload (default); batched: many models in one call; "
-                         "surrogate: the learned part on the d=300 workload")
+                         "surrogate: the learned part on the d=300 workload; grad: values and gradients "
+                         "on the d=20 workload")
     ap.add_argument("--models", type=int, default=64, help="batched: number of models")
     ap.add_argument("--train-points", type=int, default=2_000_000, help="surrogate: interpolant training pairs")
     ap.add_argument("--epochs", type=int, default=3, help="surrogate: passes over the training pairs")
@@ -90,6 +91,8 @@ def main():
         return bench_batched(args)
     if args.workload == "surrogate":
         return bench_surrogate(args)
+    if args.workload == "grad":
+        return bench_grad(args)
 
     import torch
 
@@ -114,8 +117,9 @@ def main():
     model = hd.asg_build_components(cfg["d"], cfg["m"], cfg["anchor"], (tf.c_fn, tf.c_user), comps=cfg["comps"],
                                     max_level=cfg["max_level"], eps_gamma=cfg["eps_gamma"])
     info = hd.hdmr_get_info(model)
+    build_s = time.time() - t0
     log("built model on device in %.1f s: %d components, %d rows, %d passes, %.2f GB" %
-        (time.time() - t0, info["n_components"], info["n_rows"], info["n_passes"], info["device_bytes"] / 1e9))
+        (build_s, info["n_components"], info["n_rows"], info["n_passes"], info["device_bytes"] / 1e9))
     X = torch.from_numpy(ws.points_for(cfg, n=n)).to(dev)
     m, d = cfg["m"], cfg["d"]
     Y = torch.empty((n, m), dtype=torch.float64, device=dev)
@@ -198,6 +202,7 @@ def main():
                         (args.config, d, info["n_components"], d, info["n_components"] - d, cfg["max_level"],
                          cfg["eps_gamma"], m, n, args.precision),
             "grid_rows": info["n_rows"],
+            "build_s_untimed": build_s,
             "nonzeros_per_point": hits / n,
             "lookups_per_point": probes / n,
             "parallelism": "single GPU (points)",
@@ -261,6 +266,39 @@ def bench_batched(args):
         "roofline": {"bound": "mfma", "achieved": flops / t / 1e12, "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
                      "frac": flops / t / FP64_PEAK, "traffic": None, "kernel": "k_eval_batched (persistent)",
                      "note": "whole call timed; FP64 vector FMA work of the gather kernel"},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_grad(args):
+    """Values and gradients (hdmr_eval_grad) on the d=20 workload: 20 + 190
+    components, adaptive L=7, m=11, 1e6 next-state points; the gradient is
+    n x d x m FP64."""
+    import torch
+
+    import paper_2202_06555_amd as hd
+    import workloads.synth as ws
+
+    hd.hdmr_init(0)
+    cfg = ws.config("c2")
+    tf = ws.test_function_for(cfg)
+    model = hd.asg_build_components(cfg["d"], cfg["m"], cfg["anchor"], (tf.c_fn, tf.c_user), comps=cfg["comps"],
+                                    max_level=cfg["max_level"], eps_gamma=cfg["eps_gamma"])
+    n, d, m = cfg["n"], cfg["d"], cfg["m"]
+    X = torch.from_numpy(ws.points_for(cfg)).to("cuda:0")
+    Y = torch.empty((n, m), dtype=torch.float64, device="cuda:0")
+    G = torch.empty((n, d, m), dtype=torch.float64, device="cuda:0")
+    t = _timed(lambda: hd.hdmr_eval_grad(model, X, Y, G), args.steps, args.warmup)
+    out = {
+        "metric": "HDMR-ASG point x output value+gradient evaluations/sec at d=20, m=11",
+        "value": n * m / t, "unit": "point*outputs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "c2: d=20, 210 components, adaptive L=7 eps_gamma=1e-4, m=11, 1e6 next-state "
+                               "points; gradient n x d x m FP64", "grid_rows": hd.hdmr_get_info(model)["n_rows"]},
+        "roofline": {"bound": "hbm", "achieved": n * d * m * 8.0 / t / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": n * d * m * 8.0 / t / HBM_PEAK, "traffic": None, "kernel": "k_eval_grad_fp64",
+                     "note": "gradient output bytes only (the dominant write)"},
     }
     print(json.dumps(out), flush=True)
 
