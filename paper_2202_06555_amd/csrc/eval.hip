@@ -431,6 +431,14 @@ int hdmr_eval_grad(const hdmr_model *model, const double *points, int64_t n, dou
   if (n == 0) return HDMR_OK;
   if ((rc = set_device_of(model))) return rc;
   hipStream_t stream = (hipStream_t)stream_;
+  if (use_sorted_path(model, n)) {
+    // values are produced alongside; a scratch buffer stands in when not wanted
+    double *F = values;
+    if (!F) HDMR_HIP(hipMallocAsync((void **)&F, sizeof(double) * (size_t)n * model->m, stream));
+    rc = eval_sorted(model, points, n, F, HDMR_PLAIN_FP64, stream, 0, grad);
+    if (!values) (void)hipFreeAsync(F, stream);
+    return rc;
+  }
   const ModelView M = model->view();
   const int64_t total = n * (int64_t)M.d * M.m;
   hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 65536)), dim3(256), 0, stream,

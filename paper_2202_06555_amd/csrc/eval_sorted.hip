@@ -111,6 +111,11 @@ __global__ void k_gather_sorted(const double *__restrict__ XT, int64_t n, Pass P
   }
 }
 
+__global__ void k_zero_f64(double *__restrict__ a, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = 0.0;
+}
+
 __global__ void k_write_c0(double *__restrict__ F, const double *__restrict__ c0, int64_t n, int m) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * m; i += (int64_t)gridDim.x * blockDim.x)
     F[i] = c0[i % m];
@@ -289,6 +294,40 @@ __device__ __forceinline__ double row_weight(const CellRow &R, const uint4 &ix, 
   return w;
 }
 
+// Derivative weight of a row with respect to the key coordinate at position
+// qpos: w_S phi'(x_qpos) prod_{other q} phi(x_q) (eq (3.1), eq (3.2)), with
+// phi' the right derivative (the left one at x = 1), zero outside [0,1] and
+// zero unless the row holds the point's active cell c = min(floor(x 2^l),
+// 2^l - 1) at its level in that dimension; zero if the row's component
+// does not contain that dimension.
+__device__ __forceinline__ double row_dweight(const CellRow &R, const uint4 &ix, double x0, double x1, double x2,
+                                              double x3, int qpos) {
+  const uint32_t iv[KMAX] = {ix.x, ix.y, ix.z, ix.w};
+  double w = (double)R.w;
+  bool has = false;
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    if (q < R.k) {
+      const int p = R.pos[q];
+      double x = x0;
+      x = p == 1 ? x1 : x;
+      x = p == 2 ? x2 : x;
+      x = p == 3 ? x3 : x;
+      const double scale = (double)(1u << R.lv[q]);
+      const double t = x * scale - (double)iv[q];
+      if (p == qpos) {
+        has = true;
+        const double cf = fmin(fmax(floor(x * scale), 0.0), scale - 1.0);
+        const bool active = (((uint32_t)cf) | 1u) == iv[q];
+        w *= (active && x >= 0.0 && x <= 1.0) ? (t >= 0.0 ? -scale : scale) : 0.0;
+      } else {
+        w *= fmax(0.0, 1.0 - fabs(t));
+      }
+    }
+  }
+  return has ? w : 0.0;
+}
+
 
 // A work item of the contraction is a chunk of <= CHUNK consecutive sorted
 // points of one cell (record: first sorted point, count, rows of the cell,
@@ -385,11 +424,11 @@ __device__ __forceinline__ uint4 tile_rec(const uint4 *__restrict__ tiles, int64
 
 // Adds a wave's MFMA result for one sub-tile to the outputs: lane value
 // (group mt, register i) belongs to point mt * 16 + r0 + i * rs of the
-// sub-tile and output col.  Plain loads and stores: within a pass each
+// sub-tile and output col; point p's row starts at F + p * m.  Plain loads and stores: within a pass each
 // (point, output) has exactly one writer and passes are separate launches in
 // stream order.  Two halves of 8 loads keep the live registers bounded.
-template <typename V>
-__device__ __forceinline__ void add_rows(double *__restrict__ F, const int32_t *pid, int m, int col, int cnt, int r0,
+template <typename V, typename S>
+__device__ __forceinline__ void add_rows(double *__restrict__ F, const int32_t *pid, S m, int col, int cnt, int r0,
                                          int rs, const V (&acc)[4]) {
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -412,13 +451,17 @@ __device__ __forceinline__ void add_rows(double *__restrict__ F, const int32_t *
 }
 
 // Plain FP64 contraction: FP64 weights in LDS (MFMA A operand, shared by the
-// waves), FP64 surplus operands (B) in registers, FP64 MFMA 16x16x4.
-template <int TR>
+// waves), FP64 surplus operands (B) in registers, FP64 MFMA 16x16x4.  With
+// GRAD, every sub-tile step also forms the derivative weights of each key
+// dimension q (row_dweight) and adds their products with the same surplus
+// operands to the gradient rows G + p * d m + dims[q] m (G: n x d x m).
+template <int TR, bool GRAD>
 __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const uint4 *__restrict__ tiles,
                                                       const uint32_t *__restrict__ ntiles_p,
                                                       const CellRow *__restrict__ list, const uint4 *__restrict__ idx,
                                                       const int32_t *__restrict__ spid, const double *__restrict__ sx,
-                                                      int64_t n, double *__restrict__ F, int o0) {
+                                                      int64_t n, double *__restrict__ F, int o0,
+                                                      double *__restrict__ G) {
   constexpr int WS = TR + 4;  // W row stride (doubles): spreads A-operand reads over the LDS banks
   __shared__ double s_w[TPTS][WS];
   __shared__ RowsLds<TR> s_rows[2];
@@ -518,6 +561,34 @@ __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const
           }
           // lane holds rows kk + 4 i of each 16-point group, column jj
           if (col < m) add_rows(F, SP.pid, m, col, cnt, kk, 4, acc);
+        }
+        if constexpr (GRAD) {
+          // derivative weights of key dimension q, same surplus operands,
+          // added to the gradient rows of that dimension
+          for (int q = 0; q < P.k; ++q) {
+            __syncthreads();  // the previous MFMAs are done with s_w
+            {
+              const int pt = t >> 2, grp = t & 3;
+              const double x0 = SP.xs[pt][0], x1 = SP.xs[pt][1], x2 = SP.xs[pt][2], x3 = SP.xs[pt][3];
+              for (int r = grp; r < Rp; r += 4)
+                s_w[pt][r] = (r < Rb && pt < cnt) ? row_dweight(SR.rows[r], SR.ix[r], x0, x1, x2, x3, q) : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) acc[mt] = v4d{0.0, 0.0, 0.0, 0.0};
+            if (wave_on) {
+#pragma unroll
+              for (int j = 0; j < TR / 4; ++j) {
+                if (4 * j < Rp) {
+#pragma unroll
+                  for (int mt = 0; mt < 4; ++mt)
+                    acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[mt * 16 + jj][4 * j + kk], b[j], acc[mt], 0, 0, 0);
+                  __builtin_amdgcn_sched_barrier(0);
+                }
+              }
+              if (col < m) add_rows(G + (int64_t)P.dims[q] * m, SP.pid, (int64_t)M.d * m, col, cnt, kk, 4, acc);
+            }
+          }
         }
         pb ^= 1;
       }
@@ -693,11 +764,12 @@ int ws_alloc(T **p, size_t count, hipStream_t s) {
 }  // namespace
 
 int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, int precision, hipStream_t stream,
-                int variant) {
+                int variant, double *G) {
   const ModelView M = model->view();
   const int d = M.d, m = M.m;
   if (n >= (int64_t)INT32_MAX) return fail(HDMR_EUNSUPPORTED, "n >= 2^31 points in one call");
   if (precision == HDMR_MIXED && !model->alpha32) return fail(HDMR_EUNSUPPORTED, "model has no FP32 surpluses");
+  if (G && precision != HDMR_PLAIN_FP64) return fail(HDMR_EUNSUPPORTED, "gradients are FP64 only");
   int64_t list_max = 1;
   for (const Pass &P : model->passes) list_max = std::max<int64_t>(list_max, P.list_bound);
   if (list_max >= (int64_t)UINT32_MAX) return fail(HDMR_EUNSUPPORTED, "cell row lists exceed 2^32 entries");
@@ -743,6 +815,7 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
   hipLaunchKernelGGL(k_transpose, dim3((unsigned)((n + 31) / 32), (unsigned)((d + 31) / 32)), dim3(256), 0, stream,
                      X, n, d, xt, nanflag);
   hipLaunchKernelGGL(k_write_c0, dim3(gs), dim3(256), 0, stream, F, M.c0, n, m);
+  if (G) hipLaunchKernelGGL(k_zero_f64, dim3(gs), dim3(256), 0, stream, G, n * d * m);
   hipError_t e = hipSuccess;
   for (const Pass &P : model->passes) {
     const int nbins = 1 << P.key_bits;
@@ -779,12 +852,15 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
     {
       StageTimer tm(STAGE_CONTRACT, stream);
       for (int o0 = 0; o0 < m; o0 += 64) {
-        if (precision == HDMR_PLAIN_FP64 && variant == 0)
-          hipLaunchKernelGGL(k_tile_fp64<TR_FP64>, dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles, clist,
-                             cidx, spid, sxv, n, F, o0);
+        if (G)
+          hipLaunchKernelGGL((k_tile_fp64<TR_FP64, true>), dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles,
+                             clist, cidx, spid, sxv, n, F, o0, G);
+        else if (precision == HDMR_PLAIN_FP64 && variant == 0)
+          hipLaunchKernelGGL((k_tile_fp64<TR_FP64, false>), dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles,
+                             clist, cidx, spid, sxv, n, F, o0, (double *)nullptr);
         else if (precision == HDMR_PLAIN_FP64)
-          hipLaunchKernelGGL(k_tile_fp64<TR_FP64_ALT>, dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles,
-                             clist, cidx, spid, sxv, n, F, o0);
+          hipLaunchKernelGGL((k_tile_fp64<TR_FP64_ALT, false>), dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles,
+                             ntiles, clist, cidx, spid, sxv, n, F, o0, (double *)nullptr);
         else if (variant == 0)
           hipLaunchKernelGGL(k_tile_mixed<TR_MIXED>, dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles,
                              clist, cidx, spid, sxv, (const float *)model->alpha32, n, F, o0);
@@ -796,6 +872,7 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
   }
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_nan_fix, dim3(gs), dim3(256), 0, stream, F, nanflag, n, m);
+    if (G) hipLaunchKernelGGL(k_nan_fix, dim3(gs), dim3(256), 0, stream, G, nanflag, n, d * m);
     e = hipGetLastError();
   }
   release();

@@ -140,12 +140,14 @@ int make_model(int32_t d, int32_t m, const double *c0, const std::vector<HostCom
                const DeviceAlphaSource *dsrc = nullptr);
 
 int set_device_of(const hdmr_model *model);
+void keep_pool_memory(int device);
 
 // Cell-sorted evaluation (eval_sorted.hip), precision HDMR_PLAIN_FP64 or
 // HDMR_MIXED; variant 0 uses the default row batch of the contraction, 1 the
-// smaller alternative.
+// smaller alternative.  With G (n x d x m, plain precision only) the
+// gradient is computed as well.
 int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, int precision, hipStream_t stream,
-                int variant = 0);
+                int variant = 0, double *G = nullptr);
 
 // Drop every cached batched-launch graph that refers to the model (batched.hip).
 void batched_forget(const hdmr_model *model);

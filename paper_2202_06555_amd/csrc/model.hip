@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 
 #include "hdmr_internal.h"
@@ -27,7 +28,27 @@ int set_device_of(const hdmr_model *model) {
   int cur = -1;
   HDMR_HIP(hipGetDevice(&cur));
   if (cur != model->device) HDMR_HIP(hipSetDevice(model->device));
+  keep_pool_memory(model->device);
   return HDMR_OK;
+}
+
+// Evaluation workspaces (several GB for large batches) come from the device's
+// default stream-ordered pool; keeping freed blocks in the pool (instead of
+// returning them at every synchronisation) makes repeated evaluations reuse
+// them.  Set once per device.
+void keep_pool_memory(int device) {
+  static std::mutex mu;
+  static std::vector<char> done;
+  std::lock_guard<std::mutex> lk(mu);
+  if (device < 0) return;
+  if ((int)done.size() <= device) done.resize((size_t)device + 1, 0);
+  if (done[(size_t)device]) return;
+  done[(size_t)device] = 1;
+  hipMemPool_t pool = nullptr;
+  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess && pool) {
+    uint64_t threshold = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold);
+  }
 }
 
 namespace {

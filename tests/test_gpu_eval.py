@@ -162,3 +162,28 @@ def test_c2_full_size_sampled(hd):
     err = np.abs(Y.cpu().numpy()[idx] - ref).max()
     print("c2 sampled max |err| = %.3e" % err)
     assert err <= TOL
+
+
+def test_c2_full_size_gradient_sampled(hd, eval_path):
+    # values and gradients at 1e6 next-state points, checked on 1000 sampled points
+    if eval_path == "gather":
+        pytest.skip("the full-size gradient runs once, on the path the library picks by size")
+    import os
+    import torch
+    os.environ.pop("HDMR_EVAL_PATH", None)
+    cfg = ws.config("c2")
+    tf = ws.test_function_for(cfg)
+    model, _ = oracle.build_model(cfg["comps"], cfg["d"], cfg["m"], cfg["anchor"], (tf.c_fn, tf.c_user),
+                                  max_level=cfg["max_level"], eps_gamma=cfg["eps_gamma"])
+    X = ws.points_for(cfg)
+    gm = hd.hdmr_model_from_surpluses(model)
+    Y, G = hd.hdmr_eval_grad(gm, _dev(X))
+    torch.cuda.synchronize()
+    idx = np.concatenate([np.random.default_rng(5).choice(X.shape[0], 1000, replace=False), np.arange(20)])
+    ry, rg = oracle.gradient(model, X[idx])
+    np.testing.assert_allclose(Y.cpu().numpy()[idx], ry, rtol=0, atol=TOL)
+    g = G.cpu().numpy()[idx]
+    scale = max(1.0, np.abs(rg).max())
+    err = np.abs(g - rg).max()
+    print("c2 gradient sampled max |err| = %.3e (scale %.1f)" % (err, scale))
+    assert err <= TOL * scale
