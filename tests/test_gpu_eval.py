@@ -187,3 +187,18 @@ def test_c2_full_size_gradient_sampled(hd, eval_path):
     err = np.abs(g - rg).max()
     print("c2 gradient sampled max |err| = %.3e (scale %.1f)" % (err, scale))
     assert err <= TOL * scale
+
+
+def test_four_dim_components(hd):
+    # components of every order up to 4: passes with four key dimensions
+    # (4-bit cells, several candidate rows per level multi-index)
+    rng = np.random.default_rng(12)
+    model = ws.synthetic_regular_model(d=5, m=6, order=4, ell=5, seed=12)
+    X = np.vstack([_special_points(5, rng, 200), rng.random((20000, 5))])
+    _, Y = _eval(hd, model, X)
+    np.testing.assert_allclose(Y, oracle.evaluate(model, X), rtol=0, atol=TOL)
+    gm = hd.hdmr_model_from_surpluses(model)
+    Ym = hd.hdmr_eval(gm, _dev(X), precision=hd.MIXED).cpu().numpy()
+    ref = oracle.evaluate(model, X)
+    ok = ~np.isnan(X).any(axis=1)
+    assert np.linalg.norm(Ym[ok] - ref[ok]) <= 1e-6 * np.linalg.norm(ref[ok])
