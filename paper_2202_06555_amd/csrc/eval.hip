@@ -69,13 +69,18 @@ __global__ __launch_bounds__(256) void k_eval_fp64(ModelView M, const double *__
     double acc[OPL];
 #pragma unroll
     for (int j = 0; j < OPL; ++j) acc[j] = 0.0;
+    // the descriptors do not depend on the point: the next group's are loaded
+    // while the current group is processed
+    TupDesc Tn{};
+    if (lane < M.ntup) Tn = M.tups[lane];
     for (int t0 = 0; t0 < M.ntup; t0 += WAVE) {
       // ---- lookup: one tuple per lane ----
       const int t = t0 + lane;
+      const TupDesc T = Tn;
+      if (t + WAVE < M.ntup) Tn = M.tups[t + WAVE];
       int32_t row = -1;
       double w = 0.0;
       if (t < M.ntup) {
-        const TupDesc T = M.tups[t];
         w = T.w;
         uint32_t slot = 0;
 #pragma unroll
