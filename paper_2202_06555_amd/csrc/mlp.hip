@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/hdmr_surrogate.h"
@@ -23,6 +24,10 @@ constexpr int NL = 4;          // linear layers
 constexpr int TM = 64, TN = 64, TK = 32;
 constexpr int LK = TK + 8;     // LDS row stride (bf16): 80-byte rows keep 16-byte alignment
 constexpr int CHUNK_ROWS = 65536;  // rows per inference chunk
+constexpr int DW_SPLIT_MAX = 16;    // K slices of the weight-gradient GEMM
+constexpr int DW_BLOCKS = 512;      // workgroups the split aims for
+constexpr int COLSUM_CHUNKS = 64;   // row chunks of the bias-gradient reduction
+constexpr int WIDE128_MIN_TILES = 1024;  // workgroups of the 128 x 128 tile kernel (four per CU)
 
 inline int64_t pad8(int64_t x) { return (x + 7) & ~(int64_t)7; }
 
@@ -48,8 +53,9 @@ struct Gemm {
   int64_t ldz;
   bf16 *H;            // HIDDEN: GELU(z) out; DH: dz out
   int64_t ldh;
-  float *C;           // OUT, DW
+  float *C;           // OUT, DW (DW: slice z writes C + z * M * ldc)
   int64_t ldc;
+  int kslice;         // K per workgroup slice along blockIdx.z (a multiple of TK)
 };
 
 // Stage a 64 x 32 tile of a [rows][k] operand into LDS (row-major, k
@@ -84,6 +90,57 @@ __device__ __forceinline__ void stage(bf16 (*dst)[LK], const bf16 *__restrict__ 
   }
 }
 
+// Bias of the NB column tiles a lane stores (HIDDEN, OUT), loaded up front.
+template <int EPI, int NB>
+__device__ __forceinline__ void load_bias(const Gemm &g, int c0, int i, float (&bv)[NB]) {
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int col = c0 + 16 * b + i;
+    bv[b] = ((EPI == EPI_HIDDEN || EPI == EPI_OUT) && col < g.N) ? g.bias[col] : 0.f;
+  }
+}
+
+// Fused epilogue of a wave's NA x NB MFMA tiles (rows r0 + 16 a + 4 kg + r,
+// columns c0 + 16 b + i).  Every operand is read before the first store, so
+// the loads overlap instead of each waiting behind a store it might alias.
+template <int EPI, int NA, int NB>
+__device__ __forceinline__ void store_tiles(const Gemm &g, const f32x4 (&acc)[NA][NB], int r0, int c0, int i, int kg,
+                                            const float (&bv)[NB]) {
+  float zv[NA][NB][4];
+  if constexpr (EPI == EPI_DH) {
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + 16 * a + 4 * kg + r, col = c0 + 16 * b + i;
+          zv[a][b][r] = (row < g.M && col < g.N) ? g.Z[(int64_t)row * g.ldz + col] : 0.f;
+        }
+  }
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + 16 * a + 4 * kg + r, col = c0 + 16 * b + i;
+        if (row >= g.M || col >= g.N) continue;
+        const float v = acc[a][b][r];
+        if constexpr (EPI == EPI_HIDDEN) {
+          const float z = v + bv[b];
+          if (g.Z) g.Z[(int64_t)row * g.ldz + col] = z;
+          g.H[(int64_t)row * g.ldh + col] = (bf16)gelu_f(z);
+        } else if constexpr (EPI == EPI_OUT) {
+          g.C[(int64_t)row * g.ldc + col] = v + bv[b];
+        } else if constexpr (EPI == EPI_DH) {
+          g.H[(int64_t)row * g.ldh + col] = (bf16)(v * gelu_grad_f(zv[a][b][r]));
+        } else {
+          g.C[((int64_t)blockIdx.z * g.M + row) * g.ldc + col] = v;  // slice blockIdx.z of a split-K product
+        }
+      }
+}
+
 // 64 x 64 output tile per workgroup of 4 waves; each wave a 32 x 32 quarter
 // (2 x 2 MFMA 16x16x32 tiles).
 template <int TA, int TB, int EPI>
@@ -94,12 +151,15 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
   const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
   const int i = lane & 15, kg = lane >> 4;
+  float bv[2];
+  load_bias<EPI, 2>(g, n0 + wn, i, bv);
   f32x4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < g.K; k0 += TK) {
+  const int kb = blockIdx.z * g.kslice, ke = min(g.K, kb + g.kslice);
+  for (int k0 = kb; k0 < ke; k0 += TK) {
     __syncthreads();
     stage<TA == 0>(sA, g.A, g.lda, m0, k0, g.M, g.K, t);
     stage<TB == 1>(sB, g.B, g.ldb, n0, k0, g.N, g.K, t);
@@ -115,38 +175,223 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
       for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
   }
   // lane holds rows 4 kg + r, column i of each 16 x 16 tile
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm + 16 * a + 4 * kg + r, col = n0 + wn + 16 * b + i;
-        if (row >= g.M || col >= g.N) continue;
-        const float v = acc[a][b][r];
-        if (EPI == EPI_HIDDEN) {
-          const float z = v + g.bias[col];
-          if (g.Z) g.Z[(int64_t)row * g.ldz + col] = z;
-          g.H[(int64_t)row * g.ldh + col] = (bf16)gelu_f(z);
-        } else if (EPI == EPI_OUT) {
-          g.C[(int64_t)row * g.ldc + col] = v + g.bias[col];
-        } else if (EPI == EPI_DH) {
-          g.H[(int64_t)row * g.ldh + col] = (bf16)(v * gelu_grad_f(g.Z[(int64_t)row * g.ldz + col]));
-        } else {
-          g.C[(int64_t)row * g.ldc + col] = v;
-        }
-      }
+  store_tiles<EPI, 2, 2>(g, acc, m0 + wm, n0 + wn, i, kg, bv);
 }
 
-// Rows idx[r] (or r when idx is NULL) of X (n x d, FP64) -> H (rows x ldh, BF16).
+// Large-tile kernel for tall products: a (2 WT) x (2 WT) output tile per
+// workgroup of 4 waves, each wave a WT x WT quarter of (WT/16)^2 MFMA tiles,
+// k in steps of 64 through two LDS buffers; the next step is fetched into
+// registers while the current one is multiplied (one barrier per step).
+// Launched with WT = 64 (two workgroups per CU); WT = 128 (one workgroup,
+// accumulators in AGPRs) measured slower on the network's products.
+constexpr int BK = 64, LB = BK;  // 128-byte LDS rows, swizzled
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// LDS position of column col of an operand row: the 16-byte piece q of row
+// r sits at piece q ^ ((r >> 1) & 7), so the 16 rows one MFMA operand read
+// touches (and the two rows a 16-lane store touches) hit distinct banks.
+__device__ __forceinline__ int lds_col(int row, int col) { return (((col >> 3) ^ ((row >> 1) & 7)) << 3) | (col & 7); }
+
+// P 16-byte pieces per thread of a ROWS x 64 operand tile; KC as in stage().
+// Rows at or past R and k at or past kend read as zero.  Row strides are
+// multiples of 8 elements that cover the stored width, so a piece read from
+// a clamped address stays inside its row; nv[j] counts its valid elements
+// and put_tile() masks off the rest once the load has landed.
+template <int KC, int ROWS>
+__device__ __forceinline__ void fetch_tile(u32x4 (&r)[ROWS / 32], int (&nv)[ROWS / 32], const bf16 *__restrict__ src,
+                                           int64_t ld, int r0, int k0, int R, int kend, int t) {
+  constexpr int PK = ROWS / 8;  // pieces per k when rows are contiguous
+#pragma unroll
+  for (int j = 0; j < ROWS / 32; ++j) {
+    const int c = t + 256 * j;
+    int64_t off;
+    if (KC) {
+      const int gr = r0 + (c >> 3), gk = k0 + (c & 7) * 8;
+      nv[j] = gr < R ? kend - gk : 0;
+      off = (int64_t)min(gr, R - 1) * ld + min((int64_t)gk, ld - 8);
+    } else {
+      const int gk = k0 + c / PK, gr = r0 + (c % PK) * 8;
+      nv[j] = gk < kend ? R - gr : 0;
+      off = (int64_t)min(gk, kend - 1) * ld + min((int64_t)gr, ld - 8);
+    }
+    r[j] = *reinterpret_cast<const u32x4 *>(src + off);
+  }
+}
+
+template <int KC, int ROWS>
+__device__ __forceinline__ void put_tile(bf16 (*dst)[LB], const u32x4 (&r)[ROWS / 32], const int (&nv)[ROWS / 32],
+                                         int t) {
+  constexpr int PK = ROWS / 8;
+#pragma unroll
+  for (int j = 0; j < ROWS / 32; ++j) {
+    const int c = t + 256 * j;
+    u32x4 v = r[j];
+    if (nv[j] < 8) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] &= (2 * q < nv[j] ? 0xFFFFu : 0u) | (2 * q + 1 < nv[j] ? 0xFFFF0000u : 0u);
+    }
+    if (KC) {
+      const int row = c >> 3;
+      *reinterpret_cast<u32x4 *>(&dst[row][lds_col(row, (c & 7) * 8)]) = v;
+    } else {
+      const bf16x8 e8 = __builtin_bit_cast(bf16x8, v);
+      const int rv = (c % PK) * 8, k = c / PK;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) dst[rv + e][lds_col(rv + e, k)] = e8[e];
+    }
+  }
+}
+
+// One 64-deep k step of a wave's WT x WT quarter from LDS.
+template <int WT>
+__device__ __forceinline__ void mma_tile(const bf16 (*sa)[LB], const bf16 (*sb)[LB], f32x4 (&acc)[WT / 16][WT / 16],
+                                         int wm, int wn, int i, int kg) {
+  constexpr int NT = WT / 16;
+#pragma unroll
+  for (int ks = 0; ks < BK; ks += 32) {
+    bf16x8 av[NT], bv[NT];
+#pragma unroll
+    for (int a = 0; a < NT; ++a) {
+      const int row = wm + 16 * a + i;
+      av[a] = *reinterpret_cast<const bf16x8 *>(&sa[row][lds_col(row, ks + 8 * kg)]);
+    }
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+      const int row = wn + 16 * b + i;
+      bv[b] = *reinterpret_cast<const bf16x8 *>(&sb[row][lds_col(row, ks + 8 * kg)]);
+    }
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+      for (int b = 0; b < NT; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+  }
+}
+
+template <int WT>
+constexpr size_t tile_lds_bytes() {
+  // operands (two buffers of 2 WT rows each for A and B) or half the output
+  // tile (WT rows of 2 WT FP32 values plus a 16-byte pad)
+  return std::max<size_t>(2 * 4 * WT * LB * sizeof(bf16), (size_t)WT * (2 * WT + 4) * sizeof(float));
+}
+
+template <int TA, int TB, int EPI, int WT>
+__global__ __launch_bounds__(256, WT == 64 ? 2 : 1) void k_gemm_wide(Gemm g) {
+  constexpr int NT = WT / 16, BT = 2 * WT;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[tile_lds_bytes<WT>()];
+  bf16 (*sA)[BT][LB] = reinterpret_cast<bf16 (*)[BT][LB]>(lds);
+  bf16 (*sB)[BT][LB] = reinterpret_cast<bf16 (*)[BT][LB]>(lds + 2 * BT * LB * sizeof(bf16));
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  // consecutive workgroups land on different XCDs (each with its own L2):
+  // give every XCD a contiguous run of tiles so the tiles sharing a row
+  // block of A share that L2
+  const int gx = (int)gridDim.x, T = gx * (int)gridDim.y;
+  int L = (int)blockIdx.x + gx * (int)blockIdx.y;
+  if ((T & 7) == 0) L = (L & 7) * (T >> 3) + (L >> 3);
+  const int m0 = (L / gx) * BT, n0 = (L % gx) * BT;
+  const int wm = (w >> 1) * WT, wn = (w & 1) * WT;
+  const int i = lane & 15, kg = lane >> 4;
+  const int kb = blockIdx.z * g.kslice, ke = min(g.K, kb + g.kslice);
+  float bv[NT];
+  load_bias<EPI, NT>(g, n0 + wn, i, bv);
+  f32x4 acc[NT][NT];
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (kb < ke) {
+    u32x4 ra[BT / 32], rb[BT / 32];
+    int nra[BT / 32], nrb[BT / 32];
+    fetch_tile<TA == 0, BT>(ra, nra, g.A, g.lda, m0, kb, g.M, ke, t);
+    fetch_tile<TB == 1, BT>(rb, nrb, g.B, g.ldb, n0, kb, g.N, ke, t);
+    put_tile<TA == 0, BT>(sA[0], ra, nra, t);
+    put_tile<TB == 1, BT>(sB[0], rb, nrb, t);
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+      const bool more = k0 + BK < ke;
+      if (more) {
+        fetch_tile<TA == 0, BT>(ra, nra, g.A, g.lda, m0, k0 + BK, g.M, ke, t);
+        fetch_tile<TB == 1, BT>(rb, nrb, g.B, g.ldb, n0, k0 + BK, g.N, ke, t);
+      }
+      mma_tile<WT>(sA[cur], sB[cur], acc, wm, wn, i, kg);
+      if (more) {
+        put_tile<TA == 0, BT>(sA[cur ^ 1], ra, nra, t);
+        put_tile<TB == 1, BT>(sB[cur ^ 1], rb, nrb, t);
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+  }
+  if constexpr (EPI == EPI_HIDDEN || EPI == EPI_OUT) {
+    // Stage the FP32 products plus bias in LDS, one half of the tile (the
+    // rows of two waves) at a time, then sweep whole rows: each thread takes
+    // 4 consecutive values, applies the activation and writes them as one
+    // piece.  Lane-scattered 2- or 4-byte stores would split every cache
+    // line of the output between several store instructions.  Columns past
+    // N hold zeros (masked operands, zero bias) and are written to H and C
+    // only up to their padded row strides.
+    constexpr int TS = BT + 4;      // LDS row stride (floats) of the staged half
+    constexpr int PPR = BT / 4;     // 4-value pieces per row
+    static_assert((size_t)WT * TS * sizeof(float) <= sizeof(lds), "output half exceeds LDS");
+    float *tile = reinterpret_cast<float *>(lds);
+#pragma unroll 1
+    for (int half = 0; half < 2; ++half) {
+      __syncthreads();
+      if ((w >> 1) == half) {
+#pragma unroll
+        for (int a = 0; a < NT; ++a)
+#pragma unroll
+          for (int b = 0; b < NT; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tile[(16 * a + 4 * kg + r) * TS + wn + 16 * b + i] = acc[a][b][r] + bv[b];
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int q = 0; q < WT * PPR / 256; ++q) {
+        const int c = t + 256 * q;
+        const int lr = c / PPR, lc = (c % PPR) * 4;
+        const int row = m0 + half * WT + lr, col = n0 + lc;
+        if (row >= g.M) continue;
+        const f32x4 z = *reinterpret_cast<const f32x4 *>(&tile[lr * TS + lc]);
+        if constexpr (EPI == EPI_HIDDEN) {
+          if (g.Z) {
+            float *zp = g.Z + (int64_t)row * g.ldz + col;
+            if (col + 4 <= g.N && (g.ldz & 3) == 0) {
+              *reinterpret_cast<f32x4 *>(zp) = z;
+            } else {
+#pragma unroll
+              for (int e = 0; e < 4; ++e)
+                if (col + e < g.N) zp[e] = z[e];
+            }
+          }
+          if (col < g.ldh) {
+            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+            bf16x4 h;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) h[e] = (bf16)gelu_f(z[e]);
+            *reinterpret_cast<bf16x4 *>(g.H + (int64_t)row * g.ldh + col) = h;
+          }
+        } else {
+          if (col < g.ldc) *reinterpret_cast<f32x4 *>(g.C + (int64_t)row * g.ldc + col) = z;
+        }
+      }
+    }
+  } else {
+    store_tiles<EPI, NT, NT>(g, acc, m0 + wm, n0 + wn, i, kg, bv);
+  }
+}
+
+// Rows idx[r] (or row0 + r when idx is NULL) of X (n x d, FP64) -> H (rows
+// x ldh, BF16).  One wave per row, lanes across its columns.
 __global__ void k_rows_to_bf16(const double *__restrict__ X, int d, const int64_t *__restrict__ idx, int64_t row0,
                                int64_t rows, bf16 *__restrict__ H, int64_t ldh) {
-  const int64_t total = rows * d;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = e / d;
-    const int q = (int)(e - r * d);
+  const int lane = threadIdx.x & 63;
+  for (int64_t r = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); r < rows;
+       r += (int64_t)gridDim.x * (blockDim.x >> 6)) {
     const int64_t src = idx ? idx[r] : row0 + r;
-    H[r * ldh + q] = (bf16)(float)X[src * d + q];
+    const double *x = X + src * d;
+    bf16 *h = H + r * ldh;
+    for (int q = lane; q < d; q += 64) h[q] = (bf16)(float)x[q];
   }
 }
 
@@ -184,13 +429,31 @@ __global__ void k_loss_grad(const float *__restrict__ out, int64_t ldo, const fl
   if (threadIdx.x == 0) atomicAdd(loss, part[0] * inv);
 }
 
-// db[c] = sum_r G[r][c].
-__global__ void k_colsum(const bf16 *__restrict__ G, int64_t ldg, int64_t rows, int N, float *__restrict__ db) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N) return;
+// Bias gradient db[c] = sum_r G[r][c] in two deterministic stages.  Stage 1:
+// workgroup (x, y) sums columns 64x .. 64x+63 over row chunk y, 4 waves on
+// interleaved rows, into part[y][c].
+__global__ __launch_bounds__(256) void k_colsum_part(const bf16 *__restrict__ G, int64_t ldg, int64_t rows, int N,
+                                                     float *__restrict__ part) {
+  __shared__ float red[4][64];
+  const int cl = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + cl;
+  const int64_t per = (rows + gridDim.y - 1) / gridDim.y;
+  const int64_t r0 = (int64_t)blockIdx.y * per, r1 = min(rows, r0 + per);
   float s = 0.f;
-  for (int64_t r = 0; r < rows; ++r) s += (float)G[r * ldg + c];
-  db[c] = s;
+  if (c < N)
+    for (int64_t r = r0 + wv; r < r1; r += 4) s += (float)G[r * ldg + c];
+  red[wv][cl] = s;
+  __syncthreads();
+  if (wv == 0 && c < N) part[(int64_t)blockIdx.y * N + c] = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
+}
+
+// Stage 2 (also the split-K reduction of the weight gradient): out[e] = sum_z part[z * len + e].
+__global__ void k_sum_slices(const float *__restrict__ part, int slices, int64_t len, float *__restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < len; e += (int64_t)gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int z = 0; z < slices; ++z) s += part[(int64_t)z * len + e];
+    out[e] = s;
+  }
 }
 
 __global__ void k_fill_f32(float *__restrict__ a, int64_t n, float v) {
@@ -221,13 +484,15 @@ __global__ void k_to_bf16(const float *__restrict__ W, int rows, int cols, bf16 
 }
 
 // Y[row0 + r][o] = out[r][o] * std[o] + mean[o] (FP64).
+// Y[r][o] = out[r][o] std[o] + mean[o] (FP64); one wave per row.
 __global__ void k_destd(const float *__restrict__ out, int64_t ldo, int64_t rows, int m, const float *__restrict__ mean,
                         const float *__restrict__ stdv, double *__restrict__ Y) {
-  const int64_t total = rows * m;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = e / m;
-    const int o = (int)(e - r * m);
-    Y[e] = (double)out[r * ldo + o] * (double)stdv[o] + (double)mean[o];
+  const int lane = threadIdx.x & 63;
+  for (int64_t r = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); r < rows;
+       r += (int64_t)gridDim.x * (blockDim.x >> 6)) {
+    const float *o_ = out + r * ldo;
+    double *y = Y + r * m;
+    for (int o = lane; o < m; o += 64) y[o] = (double)o_[o] * (double)stdv[o] + (double)mean[o];
   }
 }
 
@@ -294,12 +559,29 @@ __global__ void k_maxerr(const double *__restrict__ A, const double *__restrict_
 }
 
 unsigned grid_of(int64_t total) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 16384)); }
+// workgroups for one-wave-per-row kernels (4 rows per workgroup of 256)
+unsigned row_grid(int64_t rows) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((rows + 3) / 4, 16384)); }
 
 template <int TA, int TB, int EPI>
 hipError_t gemm(const Gemm &g, hipStream_t s) {
   if (g.M == 0 || g.N == 0) return hipSuccess;
-  const dim3 grid((unsigned)((g.N + TN - 1) / TN), (unsigned)((g.M + TM - 1) / TM));
-  hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, s, g);
+  Gemm gg = g;
+  unsigned slices = 1;
+  if (EPI == EPI_DW && gg.kslice > 0)
+    slices = (unsigned)((gg.K + gg.kslice - 1) / gg.kslice);
+  else
+    gg.kslice = std::max(gg.K, 1);
+  if constexpr (EPI != EPI_DW) {
+    // 128 x 128 tiles once they give every CU four workgroups, else 64 x 64
+    const int64_t t128 = (int64_t)((g.N + 127) / 128) * ((g.M + 127) / 128);
+    if (t128 >= WIDE128_MIN_TILES) {
+      const dim3 grid((unsigned)((g.N + 127) / 128), (unsigned)((g.M + 127) / 128), 1);
+      hipLaunchKernelGGL((k_gemm_wide<TA, TB, EPI, 64>), grid, dim3(256), 0, s, gg);
+      return hipGetLastError();
+    }
+  }
+  const dim3 grid((unsigned)((g.N + TN - 1) / TN), (unsigned)((g.M + TM - 1) / TM), slices);
+  hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, s, gg);
   return hipGetLastError();
 }
 
@@ -326,10 +608,12 @@ struct mlp_model {
   bf16 *gb[2] = {nullptr, nullptr};                    // output / pre-activation gradients (cap x pad8(max(w, m)))
   float *loss = nullptr;                               // 1 float per step slot
   int64_t loss_cap = 0;
+  float *ws = nullptr;                                 // split-K slices / bias-gradient partials
+  int64_t ws_len = 0;
 
   ~mlp_model() {
     void *ptrs[] = {p, g, mom, vel, mean, stdv, wb[0], wb[1], wb[2], wb[3], outv, tgt, gb[0], gb[1], loss,
-                    h[0], h[1], h[2], h[3], z[0], z[1], z[2]};
+                    h[0], h[1], h[2], h[3], z[0], z[1], z[2], ws};
     for (void *q : ptrs) (void)hipFree(q);
   }
 
@@ -402,12 +686,23 @@ struct mlp_model {
       dw.M = out[l];
       dw.N = in[l];
       dw.K = (int)rows;
-      dw.C = g + woff[l];
+      // split K so that the (out x in) tile grid fills the chip; slices go to ws
+      const int64_t tiles = ((out[l] + TM - 1) / TM) * ((in[l] + TN - 1) / TN);
+      const int64_t want = std::min<int64_t>(DW_SPLIT_MAX, std::max<int64_t>(1, (DW_BLOCKS + tiles - 1) / tiles));
+      dw.kslice = (int)(((rows + want - 1) / want + TK - 1) / TK * TK);
+      const int slices = (int)((rows + dw.kslice - 1) / dw.kslice);
+      const int64_t len = (int64_t)out[l] * in[l];
+      dw.C = slices > 1 ? ws : g + woff[l];
       dw.ldc = in[l];
       e = gemm<1, 0, EPI_DW>(dw, s);
       if (e != hipSuccess) break;
-      hipLaunchKernelGGL(k_colsum, dim3((unsigned)((out[l] + 255) / 256)), dim3(256), 0, s, gb[cur], gw, rows,
-                         out[l], g + boff[l]);
+      if (slices > 1)
+        hipLaunchKernelGGL(k_sum_slices, dim3(grid_of(len)), dim3(256), 0, s, ws, slices, len, g + woff[l]);
+      const int chunks = (int)std::min<int64_t>(COLSUM_CHUNKS, std::max<int64_t>(1, rows / 64));
+      hipLaunchKernelGGL(k_colsum_part, dim3((unsigned)((out[l] + 63) / 64), (unsigned)chunks), dim3(256), 0, s,
+                         gb[cur], gw, rows, out[l], ws);
+      hipLaunchKernelGGL(k_sum_slices, dim3(grid_of(out[l])), dim3(256), 0, s, ws, chunks, (int64_t)out[l],
+                         g + boff[l]);
       if (l > 0) {
         // dZ_{l-1} = (G W_l) * gelu'(Z_{l-1})
         Gemm dh{};
@@ -435,7 +730,8 @@ struct mlp_model {
   hipError_t grads(int64_t rows, float *lossp, hipStream_t s) {
     hipError_t e = forward(rows, true, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_loss_grad, dim3(grid_of(rows * m)), dim3(256), 0, s, outv, pad8(m), tgt, m, rows, gb[0],
+    // few workgroups: each adds its partial loss to one FP32 word
+    hipLaunchKernelGGL(k_loss_grad, dim3(std::min(grid_of(rows * m), 512u)), dim3(256), 0, s, outv, pad8(m), tgt, m, rows, gb[0],
                        pad8(std::max(w, m)), lossp);
     return backward(rows, s);
   }
@@ -489,11 +785,11 @@ int forward_rows(const mlp_model *cnet, const double *X, int64_t n, double *Y, h
   if (rc) return rc;
   for (int64_t r0 = 0; r0 < n; r0 += net->cap) {
     const int64_t rows = std::min<int64_t>(net->cap, n - r0);
-    hipLaunchKernelGGL(k_rows_to_bf16, dim3(grid_of(rows * net->d)), dim3(256), 0, s, X, net->d,
+    hipLaunchKernelGGL(k_rows_to_bf16, dim3(row_grid(rows)), dim3(256), 0, s, X, net->d,
                        (const int64_t *)nullptr, r0, rows, net->h[0], net->ldin[0]);
     hipError_t e = net->forward(rows, false, s);
     if (e != hipSuccess) return hip_fail(e, "mlp forward");
-    hipLaunchKernelGGL(k_destd, dim3(grid_of(rows * net->m)), dim3(256), 0, s, net->outv, pad8(net->m), rows,
+    hipLaunchKernelGGL(k_destd, dim3(row_grid(rows)), dim3(256), 0, s, net->outv, pad8(net->m), rows,
                        net->m, net->mean, net->stdv, Y + r0 * net->m);
   }
   HDMR_HIP(hipGetLastError());
@@ -546,6 +842,10 @@ int mlp_create(int32_t d, int32_t width, int32_t m, const float *params, mlp_mod
   net->loss_cap = 1;
   for (int l = 0; l < NL && e == hipSuccess; ++l)
     e = hipMalloc((void **)&net->wb[l], sizeof(bf16) * net->out[l] * net->ldin[l]);
+  int64_t wsl = (int64_t)COLSUM_CHUNKS * std::max(width, m);
+  for (int l = 0; l < NL; ++l) wsl = std::max<int64_t>(wsl, (int64_t)DW_SPLIT_MAX * net->out[l] * net->in[l]);
+  if (e == hipSuccess) e = hipMalloc((void **)&net->ws, sizeof(float) * wsl);
+  net->ws_len = wsl;
   if (e == hipSuccess) e = hipMemcpy(net->p, params, sizeof(float) * o, hipMemcpyHostToDevice);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(o)), dim3(256), 0, (hipStream_t)0, net->mom, o, 0.f);
@@ -632,7 +932,7 @@ int mlp_loss_grads(mlp_model *net, const double *X, const double *Y, const int64
   hipStream_t s = (hipStream_t)stream;
   if (!net->have_std) return fail(HDMR_EINVAL, "mlp_loss_grads: standardisation not set");
   if ((rc = net->reserve(batch))) return rc;
-  hipLaunchKernelGGL(k_rows_to_bf16, dim3(grid_of((int64_t)batch * net->d)), dim3(256), 0, s, X, net->d, idx,
+  hipLaunchKernelGGL(k_rows_to_bf16, dim3(row_grid(batch)), dim3(256), 0, s, X, net->d, idx,
                      (int64_t)0, (int64_t)batch, net->h[0], net->ldin[0]);
   hipLaunchKernelGGL(k_targets, dim3(grid_of((int64_t)batch * net->m)), dim3(256), 0, s, Y, net->m, idx,
                      (int64_t)batch, net->mean, net->stdv, net->tgt);
@@ -668,7 +968,7 @@ int mlp_train(mlp_model *net, const double *X, const double *Y, const int64_t *o
   hipError_t e = hipSuccess;
   for (int64_t st = 0; st < steps && e == hipSuccess; ++st) {
     const int64_t *idx = order + st * batch;
-    hipLaunchKernelGGL(k_rows_to_bf16, dim3(grid_of((int64_t)batch * net->d)), dim3(256), 0, s, X, net->d, idx,
+    hipLaunchKernelGGL(k_rows_to_bf16, dim3(row_grid(batch)), dim3(256), 0, s, X, net->d, idx,
                        (int64_t)0, (int64_t)batch, net->h[0], net->ldin[0]);
     hipLaunchKernelGGL(k_targets, dim3(grid_of((int64_t)batch * net->m)), dim3(256), 0, s, Y, net->m, idx,
                        (int64_t)batch, net->mean, net->stdv, net->tgt);

@@ -67,6 +67,54 @@ def test_forward_parity(env, d, w, m, n):
     assert np.abs(Y - ref).max() <= 2e-2 * scale
 
 
+@pytest.mark.parametrize("d,w,m,n", [(300, 512, 151, 40000), (45, 256, 257, 70000)])
+def test_forward_parity_large_tiles(env, d, w, m, n):
+    # enough rows for the 128 x 128 tile kernel (ragged rows, inputs and
+    # outputs), checked on sampled rows including the last tile
+    hd, sg = env
+    net, p, mean, std = _net(sg, d, w, m, seed=d)
+    X = np.random.default_rng(3).random((n, d))
+    Y = sg.mlp_forward(net, _dev(X)).cpu().numpy()
+    idx = np.concatenate([np.random.default_rng(4).choice(n, 1200, replace=False), np.arange(n - 200, n)])
+    out, _ = omlp.forward(p, X[idx], d, w, m, storage="bf16")
+    ref = out * std + mean
+    scale = np.abs(out).max() * std.max()
+    nw = np.linalg.norm((Y[idx] - ref) / std) / np.linalg.norm(out)
+    print("forward d=%d w=%d m=%d n=%d (sampled): normwise %.2e, max-abs %.2e" % (d, w, m, n, nw, np.abs(Y[idx] - ref).max()))
+    assert nw <= 4e-3
+    assert np.abs(Y[idx] - ref).max() <= 2e-2 * scale
+
+
+def _check_grads(g, rg, dims):
+    o = 0
+    for l in range(4):
+        for size in (dims[l + 1] * dims[l], dims[l + 1]):
+            a, b = g[o:o + size], rg[o:o + size]
+            nw = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+            print("layer %d tensor of %d: normwise %.2e" % (l, size, nw))
+            assert nw <= 2e-2
+            o += size
+
+
+def test_gradient_parity_large_batch(env):
+    # a batch large enough for the 128 x 128 tile kernel in the forward and
+    # in the back-propagated products, and a deep split of the weight gradient
+    hd, sg = env
+    import torch
+    d, w, m, B = 24, 128, 9, 131100
+    net, p, mean, std = _net(sg, d, w, m, seed=6)
+    rng = np.random.default_rng(7)
+    X = rng.random((140000, d))
+    Yraw = rng.normal(size=(140000, m)) * std + mean
+    idx = rng.choice(140000, B, replace=False)
+    loss, g = sg.mlp_loss_grads(net, _dev(X), _dev(Yraw), torch.from_numpy(idx.astype(np.int64)).to("cuda:0"))
+    mu32, sd32 = sg.mlp_get_standardization(net)
+    T = (Yraw[idx] - mu32.astype(np.float64)) / sd32.astype(np.float64)
+    rl, rg = omlp.loss_and_grads(p, X[idx], T, d, w, m, storage="bf16")
+    assert abs(loss - rl) <= 1e-3 * rl
+    _check_grads(g, rg, [d, w, w, w, m])
+
+
 def test_gradient_parity(env):
     hd, sg = env
     import torch
@@ -82,15 +130,7 @@ def test_gradient_parity(env):
     T = (Yraw[idx] - mu32.astype(np.float64)) / sd32.astype(np.float64)
     rl, rg = omlp.loss_and_grads(p, X[idx], T, d, w, m, storage="bf16")
     assert abs(loss - rl) <= 1e-3 * rl
-    o = 0
-    dims = [d, w, w, w, m]
-    for l in range(4):
-        for size in (dims[l + 1] * dims[l], dims[l + 1]):
-            a, b = g[o:o + size], rg[o:o + size]
-            nw = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
-            print("layer %d tensor of %d: normwise %.2e" % (l, size, nw))
-            assert nw <= 2e-2
-            o += size
+    _check_grads(g, rg, [d, w, w, w, m])
 
 
 def test_adam_step_matches_textbook_update(env):
