@@ -379,7 +379,7 @@ def bench_surrogate(args):
                    "network_only_evals_per_s": ns * m / t_mlp, "interpolant_evals_per_s": ns * m / t_int},
         "roofline": {"bound": "mfma", "achieved": flops_fwd / t_mlp / 1e12, "peak": BF16_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": flops_fwd / t_mlp / BF16_PEAK, "traffic": None,
-                     "kernel": "k_gemm (network forward)"},
+                     "kernel": "k_gemm_wide<0, 1, EPI, 64> (network forward: 128 x 128 tiles)", "note": "whole forward timed (input conversion, four products, de-standardisation); flops of the four products"},
     }
     print(json.dumps(out), flush=True)
 
