@@ -147,3 +147,31 @@ def test_c3_full_size_build_and_eval(hd):
     nw = float(np.linalg.norm(Ym - ref) / np.linalg.norm(ref))
     print("c3 mixed: sampled normwise error %.3e" % nw)
     assert nw <= 1e-6
+
+
+def test_c5_full_size_build_and_eval(hd):
+    """The surrogate's interpolant at full size: d=300, 300 + 300 components
+    (order-2 terms scaled 1/100), L=7, eps=1e-4, m=151; the GPU build against
+    the oracle's own build, then 5e5 points through the plain FP64 and mixed
+    paths, 2000 sampled points plus the first and last rows checked."""
+    import torch
+    cfg = ws.config("c5")
+    tf = ws.TestFunction(cfg["d"], cfg["m"], cfg["pairs"], cfg["seed"], ref=cfg["anchor"], pair_scale=0.01)
+    kw = dict(max_level=cfg["max_level"], eps_gamma=cfg["eps_gamma"])
+    gm = hd.asg_build_components(cfg["d"], cfg["m"], cfg["anchor"], (tf.c_fn, tf.c_user), comps=cfg["comps"], **kw)
+    model, _ = oracle.build_model(cfg["comps"], cfg["d"], cfg["m"], cfg["anchor"], (tf.c_fn, tf.c_user), **kw)
+    w = _compare_models(hd, gm, model)
+    X = ws.points_for(cfg, n=500_000, seed=2)
+    Xd = torch.from_numpy(X).to("cuda:0")
+    Y = hd.hdmr_eval(gm, Xd)
+    Ym = hd.hdmr_eval(gm, Xd, precision=hd.MIXED)
+    torch.cuda.synchronize()
+    idx = np.random.default_rng(2).choice(X.shape[0], 2000, replace=False)
+    idx = np.concatenate([idx, np.arange(20), np.arange(X.shape[0] - 20, X.shape[0])])
+    ref = oracle.evaluate(model, X[idx])
+    err = float(np.abs(Y.cpu().numpy()[idx] - ref).max())
+    nw = float(np.linalg.norm(Ym.cpu().numpy()[idx] - ref) / np.linalg.norm(ref))
+    print("c5: %d rows, surplus diff %.3e, sampled eval max |err| %.3e, mixed normwise %.3e" %
+          (hd.hdmr_get_info(gm)["n_rows"], w, err, nw))
+    assert err <= TOL
+    assert nw <= 1e-6
