@@ -198,37 +198,49 @@ __device__ __forceinline__ int lds_col(int row, int col) { return (((col >> 3) ^
 // a clamped address stays inside its row; nv[j] counts its valid elements
 // and put_tile() masks off the rest once the load has landed.
 template <int KC, int ROWS>
-__device__ __forceinline__ void fetch_tile(u32x4 (&r)[ROWS / 32], int (&nv)[ROWS / 32], const bf16 *__restrict__ src,
-                                           int64_t ld, int r0, int k0, int R, int kend, int t) {
+__device__ __forceinline__ int piece_valid(int c, int r0, int k0, int R, int kend) {
   constexpr int PK = ROWS / 8;  // pieces per k when rows are contiguous
+  if (KC) {
+    const int gr = r0 + (c >> 3), gk = k0 + (c & 7) * 8;
+    return gr < R ? kend - gk : 0;
+  }
+  const int gk = k0 + c / PK, gr = r0 + (c % PK) * 8;
+  return gk < kend ? R - gr : 0;
+}
+
+template <int KC, int ROWS>
+__device__ __forceinline__ void fetch_tile(u32x4 (&r)[ROWS / 32], const bf16 *__restrict__ src, int64_t ld, int r0,
+                                           int k0, int R, int kend, int t) {
+  constexpr int PK = ROWS / 8;
 #pragma unroll
   for (int j = 0; j < ROWS / 32; ++j) {
     const int c = t + 256 * j;
     int64_t off;
     if (KC) {
       const int gr = r0 + (c >> 3), gk = k0 + (c & 7) * 8;
-      nv[j] = gr < R ? kend - gk : 0;
       off = (int64_t)min(gr, R - 1) * ld + min((int64_t)gk, ld - 8);
     } else {
       const int gk = k0 + c / PK, gr = r0 + (c % PK) * 8;
-      nv[j] = gk < kend ? R - gr : 0;
       off = (int64_t)min(gk, kend - 1) * ld + min((int64_t)gr, ld - 8);
     }
     r[j] = *reinterpret_cast<const u32x4 *>(src + off);
   }
 }
 
+// Masks off the elements past the bounds (piece_valid(), the same geometry
+// as the fetch) and writes the pieces to LDS.
 template <int KC, int ROWS>
-__device__ __forceinline__ void put_tile(bf16 (*dst)[LB], const u32x4 (&r)[ROWS / 32], const int (&nv)[ROWS / 32],
+__device__ __forceinline__ void put_tile(bf16 (*dst)[LB], const u32x4 (&r)[ROWS / 32], int r0, int k0, int R, int kend,
                                          int t) {
   constexpr int PK = ROWS / 8;
 #pragma unroll
   for (int j = 0; j < ROWS / 32; ++j) {
     const int c = t + 256 * j;
+    const int nv = piece_valid<KC, ROWS>(c, r0, k0, R, kend);
     u32x4 v = r[j];
-    if (nv[j] < 8) {
+    if (nv < 8) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] &= (2 * q < nv[j] ? 0xFFFFu : 0u) | (2 * q + 1 < nv[j] ? 0xFFFF0000u : 0u);
+      for (int q = 0; q < 4; ++q) v[q] &= (2 * q < nv ? 0xFFFFu : 0u) | (2 * q + 1 < nv ? 0xFFFF0000u : 0u);
     }
     if (KC) {
       const int row = c >> 3;
@@ -249,7 +261,7 @@ __device__ __forceinline__ void mma_tile(const bf16 (*sa)[LB], const bf16 (*sb)[
   constexpr int NT = WT / 16;
 #pragma unroll
   for (int ks = 0; ks < BK; ks += 32) {
-    bf16x8 av[NT], bv[NT];
+    bf16x8 av[NT];
 #pragma unroll
     for (int a = 0; a < NT; ++a) {
       const int row = wm + 16 * a + i;
@@ -258,12 +270,10 @@ __device__ __forceinline__ void mma_tile(const bf16 (*sa)[LB], const bf16 (*sb)[
 #pragma unroll
     for (int b = 0; b < NT; ++b) {
       const int row = wn + 16 * b + i;
-      bv[b] = *reinterpret_cast<const bf16x8 *>(&sb[row][lds_col(row, ks + 8 * kg)]);
+      const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&sb[row][lds_col(row, ks + 8 * kg)]);
+#pragma unroll
+      for (int a = 0; a < NT; ++a) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv, acc[a][b], 0, 0, 0);
     }
-#pragma unroll
-    for (int a = 0; a < NT; ++a)
-#pragma unroll
-      for (int b = 0; b < NT; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
   }
 }
 
@@ -300,23 +310,22 @@ __global__ __launch_bounds__(256, WT == 64 ? 2 : 1) void k_gemm_wide(Gemm g) {
     for (int b = 0; b < NT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
   if (kb < ke) {
     u32x4 ra[BT / 32], rb[BT / 32];
-    int nra[BT / 32], nrb[BT / 32];
-    fetch_tile<TA == 0, BT>(ra, nra, g.A, g.lda, m0, kb, g.M, ke, t);
-    fetch_tile<TB == 1, BT>(rb, nrb, g.B, g.ldb, n0, kb, g.N, ke, t);
-    put_tile<TA == 0, BT>(sA[0], ra, nra, t);
-    put_tile<TB == 1, BT>(sB[0], rb, nrb, t);
+    fetch_tile<TA == 0, BT>(ra, g.A, g.lda, m0, kb, g.M, ke, t);
+    fetch_tile<TB == 1, BT>(rb, g.B, g.ldb, n0, kb, g.N, ke, t);
+    put_tile<TA == 0, BT>(sA[0], ra, m0, kb, g.M, ke, t);
+    put_tile<TB == 1, BT>(sB[0], rb, n0, kb, g.N, ke, t);
     __syncthreads();
     int cur = 0;
     for (int k0 = kb; k0 < ke; k0 += BK) {
       const bool more = k0 + BK < ke;
       if (more) {
-        fetch_tile<TA == 0, BT>(ra, nra, g.A, g.lda, m0, k0 + BK, g.M, ke, t);
-        fetch_tile<TB == 1, BT>(rb, nrb, g.B, g.ldb, n0, k0 + BK, g.N, ke, t);
+        fetch_tile<TA == 0, BT>(ra, g.A, g.lda, m0, k0 + BK, g.M, ke, t);
+        fetch_tile<TB == 1, BT>(rb, g.B, g.ldb, n0, k0 + BK, g.N, ke, t);
       }
       mma_tile<WT>(sA[cur], sB[cur], acc, wm, wn, i, kg);
       if (more) {
-        put_tile<TA == 0, BT>(sA[cur ^ 1], ra, nra, t);
-        put_tile<TB == 1, BT>(sB[cur ^ 1], rb, nrb, t);
+        put_tile<TA == 0, BT>(sA[cur ^ 1], ra, m0, k0 + BK, g.M, ke, t);
+        put_tile<TB == 1, BT>(sB[cur ^ 1], rb, n0, k0 + BK, g.N, ke, t);
       }
       __syncthreads();
       cur ^= 1;
