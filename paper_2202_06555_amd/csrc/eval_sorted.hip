@@ -38,7 +38,10 @@ namespace {
 
 constexpr int TPTS = 64;  // points per sub-tile (one MFMA row group per 16)
 #ifndef HDMR_TR_FP64
-#define HDMR_TR_FP64 48
+#define HDMR_TR_FP64 64
+#endif
+#ifndef HDMR_TR_GRAD
+#define HDMR_TR_GRAD 48
 #endif
 #ifndef HDMR_CHUNK
 #define HDMR_CHUNK 256
@@ -49,7 +52,9 @@ constexpr int TPTS = 64;  // points per sub-tile (one MFMA row group per 16)
 #ifndef HDMR_TILE_GRID
 #define HDMR_TILE_GRID 4096
 #endif
-constexpr int TR_FP64 = HDMR_TR_FP64;    // rows per batch, FP64 contraction
+constexpr int TR_FP64 = HDMR_TR_FP64;    // rows per batch, FP64 contraction (one output
+                                         // read-modify-write per batch: wide batches pay)
+constexpr int TR_GRAD = HDMR_TR_GRAD;    // rows per batch with the derivative chains
 constexpr int TR_MIXED = HDMR_TR_MIXED;  // rows per batch, mixed contraction
 constexpr int TR_FP64_ALT = 32;          // the alternative row batches an autotuner may pick
 constexpr int TR_MIXED_ALT = 32;
@@ -499,9 +504,9 @@ __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const
     const int count = (int)rec.y, R = (int)rec.z;
     const int nsub = (count + TPTS - 1) / TPTS;
     const int nbat = (R + TR - 1) / TR;
-    RowRegs rn{};
-    fetch_rows<TR>(rec_n, 0, t, list, idx, rn);
     if (nbat == 0) {  // no rows: nothing to add (uniform); move the next item in
+      RowRegs rn{};
+      fetch_rows<TR>(rec_n, 0, t, list, idx, rn);
       PtRegs pn{};
       fetch_pts(rec_n, 0, t, P.k, spid, sx, n, pn);
       __syncthreads();
@@ -520,12 +525,17 @@ __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const
       for (int sub = 0; sub < nsub; ++sub) {
         const bool last = bt == nbat - 1 && sub == nsub - 1;
         PtRegs pn{};
-        if (sub + 1 < nsub)
+        // the next item's first rows are fetched in this item's last step
+        // only: held across the whole item they crowd the MFMA phase
+        RowRegs rn{};
+        if (sub + 1 < nsub) {
           fetch_pts(rec, sub + 1, t, P.k, spid, sx, n, pn);
-        else if (!last)
+        } else if (!last) {
           fetch_pts(rec, 0, t, P.k, spid, sx, n, pn);
-        else
+        } else {
           fetch_pts(rec_n, 0, t, P.k, spid, sx, n, pn);
+          fetch_rows<TR>(rec_n, 0, t, list, idx, rn);
+        }
         __syncthreads();  // the previous step is done with s_w, its points and (new batch) the rows
         if (sub == 0) {
           if (bt > 0) {
@@ -869,7 +879,7 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
       StageTimer tm(STAGE_CONTRACT, stream);
       for (int o0 = 0; o0 < m; o0 += 64) {
         if (G)
-          hipLaunchKernelGGL((k_tile_fp64<TR_FP64, true>), dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles,
+          hipLaunchKernelGGL((k_tile_fp64<TR_GRAD, true>), dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles,
                              clist, cidx, spid, sxv, n, F, o0, G);
         else if (precision == HDMR_PLAIN_FP64 && variant == 0)
           hipLaunchKernelGGL((k_tile_fp64<TR_FP64, false>), dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles,
