@@ -101,8 +101,8 @@ __device__ __forceinline__ uint32_t cell_of(double x, int c) {
 }
 
 // Cell key of every point, and its key coordinates interleaved per point
-// (xk[p * k + q]) so that the gather after the sort reads one cache line
-// per point instead of one per key dimension.
+// (xk[p * k + q]): the contraction reads them by point id, one cache line
+// per point, with no sorted copy.
 __global__ void k_keys(const double *__restrict__ XT, int64_t n, Pass P, uint16_t *__restrict__ key,
                        int32_t *__restrict__ idx, double *__restrict__ xk) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
@@ -114,15 +114,6 @@ __global__ void k_keys(const double *__restrict__ XT, int64_t n, Pass P, uint16_
     }
     key[p] = (uint16_t)kk;
     idx[p] = (int32_t)p;
-  }
-}
-
-// Coordinates of the pass's key dimensions in sorted order (dimension-major).
-__global__ void k_gather_sorted(const double *__restrict__ xk, int64_t n, Pass P, const int32_t *__restrict__ spid,
-                                double *__restrict__ sx) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double *x = xk + (int64_t)spid[i] * P.k;
-    for (int q = 0; q < P.k; ++q) sx[(int64_t)q * n + i] = x[q];
   }
 }
 
@@ -396,16 +387,18 @@ __device__ __forceinline__ void store_rows(RowsLds<TR> &S, const RowRegs &g, int
 }
 
 __device__ __forceinline__ void fetch_pts(const uint4 &rec, int sub, int t, int k, const int32_t *__restrict__ spid,
-                                          const double *__restrict__ sx, int64_t n, PtRegs &g) {
+                                          const double *__restrict__ xk, int64_t n, PtRegs &g) {
   const int c = (int)rec.y - sub * TPTS;
   if (t < min(c, TPTS)) {
     const int64_t i = (int64_t)rec.x + sub * TPTS + t;
     g.pid = spid[i];
-    const double *p = sx + i;
+    // key coordinates interleaved per point (xk[pid * k + q]): one line per
+    // point, read a step before it is needed
+    const double *p = xk + (int64_t)g.pid * k;
     g.x0 = p[0];
-    g.x1 = k > 1 ? p[n] : 0.0;
-    g.x2 = k > 2 ? p[2 * n] : 0.0;
-    g.x3 = k > 3 ? p[3 * n] : 0.0;
+    g.x1 = k > 1 ? p[1] : 0.0;
+    g.x2 = k > 2 ? p[2] : 0.0;
+    g.x3 = k > 3 ? p[3] : 0.0;
   }
 }
 
@@ -474,7 +467,7 @@ template <int TR, bool GRAD>
 __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const uint4 *__restrict__ tiles,
                                                       const uint32_t *__restrict__ ntiles_p,
                                                       const CellRow *__restrict__ list, const uint4 *__restrict__ idx,
-                                                      const int32_t *__restrict__ spid, const double *__restrict__ sx,
+                                                      const int32_t *__restrict__ spid, const double *__restrict__ xk,
                                                       int64_t n, double *__restrict__ F, int o0,
                                                       double *__restrict__ G) {
   constexpr int WS = TR + 4;  // W row stride (doubles): spreads A-operand reads over the LDS banks
@@ -494,7 +487,7 @@ __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const
     RowRegs rg{};
     PtRegs pg{};
     fetch_rows<TR>(rec, 0, t, list, idx, rg);
-    fetch_pts(rec, 0, t, P.k, spid, sx, n, pg);
+    fetch_pts(rec, 0, t, P.k, spid, xk, n, pg);
     store_rows<TR>(s_rows[0], rg, t);
     store_pts(s_pts[0], pg, t);
   }
@@ -508,7 +501,7 @@ __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const
       RowRegs rn{};
       fetch_rows<TR>(rec_n, 0, t, list, idx, rn);
       PtRegs pn{};
-      fetch_pts(rec_n, 0, t, P.k, spid, sx, n, pn);
+      fetch_pts(rec_n, 0, t, P.k, spid, xk, n, pn);
       __syncthreads();
       store_rows<TR>(s_rows[rb ^ 1], rn, t);
       store_pts(s_pts[pb ^ 1], pn, t);
@@ -529,11 +522,11 @@ __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const
         // only: held across the whole item they crowd the MFMA phase
         RowRegs rn{};
         if (sub + 1 < nsub) {
-          fetch_pts(rec, sub + 1, t, P.k, spid, sx, n, pn);
+          fetch_pts(rec, sub + 1, t, P.k, spid, xk, n, pn);
         } else if (!last) {
-          fetch_pts(rec, 0, t, P.k, spid, sx, n, pn);
+          fetch_pts(rec, 0, t, P.k, spid, xk, n, pn);
         } else {
-          fetch_pts(rec_n, 0, t, P.k, spid, sx, n, pn);
+          fetch_pts(rec_n, 0, t, P.k, spid, xk, n, pn);
           fetch_rows<TR>(rec_n, 0, t, list, idx, rn);
         }
         __syncthreads();  // the previous step is done with s_w, its points and (new batch) the rows
@@ -641,7 +634,7 @@ __global__ __launch_bounds__(256, 3) void k_tile_mixed(ModelView M, Pass P, cons
                                                        const CellRow *__restrict__ list,
                                                        const uint4 *__restrict__ idx,
                                                        const int32_t *__restrict__ spid,
-                                                       const double *__restrict__ sx,
+                                                       const double *__restrict__ xk,
                                                        const float *__restrict__ alpha32, int64_t n,
                                                        double *__restrict__ F, int o0) {
   static_assert(TR % 32 == 0, "rows per batch: a multiple of the MFMA depth");
@@ -662,7 +655,7 @@ __global__ __launch_bounds__(256, 3) void k_tile_mixed(ModelView M, Pass P, cons
     RowRegs rg{};
     PtRegs pg{};
     fetch_rows<TR>(rec, 0, t, list, idx, rg);
-    fetch_pts(rec, 0, t, P.k, spid, sx, n, pg);
+    fetch_pts(rec, 0, t, P.k, spid, xk, n, pg);
     store_rows<TR>(s_rows[0], rg, t);
     store_pts(s_pts[0], pg, t);
   }
@@ -676,7 +669,7 @@ __global__ __launch_bounds__(256, 3) void k_tile_mixed(ModelView M, Pass P, cons
     fetch_rows<TR>(rec_n, 0, t, list, idx, rn);
     if (nbat == 0) {
       PtRegs pn{};
-      fetch_pts(rec_n, 0, t, P.k, spid, sx, n, pn);
+      fetch_pts(rec_n, 0, t, P.k, spid, xk, n, pn);
       __syncthreads();
       store_rows<TR>(s_rows[rb ^ 1], rn, t);
       store_pts(s_pts[pb ^ 1], pn, t);
@@ -694,11 +687,11 @@ __global__ __launch_bounds__(256, 3) void k_tile_mixed(ModelView M, Pass P, cons
         const bool last = bt == nbat - 1 && sub == nsub - 1;
         PtRegs pn{};
         if (sub + 1 < nsub)
-          fetch_pts(rec, sub + 1, t, P.k, spid, sx, n, pn);
+          fetch_pts(rec, sub + 1, t, P.k, spid, xk, n, pn);
         else if (!last)
-          fetch_pts(rec, 0, t, P.k, spid, sx, n, pn);
+          fetch_pts(rec, 0, t, P.k, spid, xk, n, pn);
         else
-          fetch_pts(rec_n, 0, t, P.k, spid, sx, n, pn);
+          fetch_pts(rec_n, 0, t, P.k, spid, xk, n, pn);
         __syncthreads();
         if (sub == 0) {
           if (bt > 0) {
@@ -802,7 +795,7 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
   if (list_max >= (int64_t)UINT32_MAX) return fail(HDMR_EUNSUPPORTED, "cell row lists exceed 2^32 entries");
   double *xt = nullptr;
   uint8_t *nanflag = nullptr;
-  double *sxv = nullptr, *xk = nullptr;
+  double *xk = nullptr;
   uint16_t *key = nullptr, *key_s = nullptr;
   int32_t *idx = nullptr, *spid = nullptr;
   uint32_t *bstart = nullptr, *bend = nullptr, *ntile = nullptr, *toff = nullptr, *ntiles = nullptr;
@@ -820,12 +813,12 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
   const size_t tmp_bytes = std::max(tmp_sort, tmp_scan);
   int rc = HDMR_OK;
   auto release = [&]() {
-    void *ptrs[] = {xt, sxv, xk, nanflag, key, key_s, idx, spid, bstart, bend, ntile, toff, ntiles, tiles, tmp,
+    void *ptrs[] = {xt, xk, nanflag, key, key_s, idx, spid, bstart, bend, ntile, toff, ntiles, tiles, tmp,
                     crows, coff, clist, cidx};
     for (void *p : ptrs) (void)hipFreeAsync(p, stream);
   };
   if ((rc = ws_alloc(&xt, (size_t)n * d, stream)) || (rc = ws_alloc(&nanflag, (size_t)n, stream)) ||
-      (rc = ws_alloc(&sxv, (size_t)n * KMAX, stream)) || (rc = ws_alloc(&xk, (size_t)n * KMAX, stream)) ||
+      (rc = ws_alloc(&xk, (size_t)n * KMAX, stream)) ||
       (rc = ws_alloc(&key, (size_t)n, stream)) || (rc = ws_alloc(&key_s, (size_t)n, stream)) ||
       (rc = ws_alloc(&idx, (size_t)n, stream)) || (rc = ws_alloc(&spid, (size_t)n, stream)) ||
       (rc = ws_alloc(&bstart, (size_t)65536, stream)) || (rc = ws_alloc(&bend, (size_t)65536, stream)) ||
@@ -856,7 +849,6 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
       if (e != hipSuccess) break;
       hipLaunchKernelGGL(k_fill2_u32, dim3(gb), dim3(256), 0, stream, bstart, bend, (int64_t)nbins);
       hipLaunchKernelGGL(k_bounds, dim3(gs), dim3(256), 0, stream, key_s, n, bstart, bend);
-      hipLaunchKernelGGL(k_gather_sorted, dim3(gs), dim3(256), 0, stream, xk, n, P, spid, sxv);
     }
     {
       // rows of every nonempty cell (count, offsets, write), then the tiles
@@ -880,22 +872,22 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
       for (int o0 = 0; o0 < m; o0 += 64) {
         if (G)
           hipLaunchKernelGGL((k_tile_fp64<TR_GRAD, true>), dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles,
-                             clist, cidx, spid, sxv, n, F, o0, G);
+                             clist, cidx, spid, xk, n, F, o0, G);
         else if (precision == HDMR_PLAIN_FP64 && variant == 0)
           hipLaunchKernelGGL((k_tile_fp64<TR_FP64, false>), dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles,
-                             clist, cidx, spid, sxv, n, F, o0, (double *)nullptr);
+                             clist, cidx, spid, xk, n, F, o0, (double *)nullptr);
         else if (precision == HDMR_PLAIN_FP64)
           hipLaunchKernelGGL((k_tile_fp64<TR_FP64_ALT, false>), dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles,
-                             ntiles, clist, cidx, spid, sxv, n, F, o0, (double *)nullptr);
+                             ntiles, clist, cidx, spid, xk, n, F, o0, (double *)nullptr);
         else if (split2)
           hipLaunchKernelGGL((k_tile_mixed<TR_MIXED, 2>), dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles,
-                             clist, cidx, spid, sxv, (const float *)model->alpha32, n, F, o0);
+                             clist, cidx, spid, xk, (const float *)model->alpha32, n, F, o0);
         else if (variant == 0)
           hipLaunchKernelGGL((k_tile_mixed<TR_MIXED, 3>), dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles,
-                             clist, cidx, spid, sxv, (const float *)model->alpha32, n, F, o0);
+                             clist, cidx, spid, xk, (const float *)model->alpha32, n, F, o0);
         else
           hipLaunchKernelGGL((k_tile_mixed<TR_MIXED_ALT, 3>), dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles,
-                             ntiles, clist, cidx, spid, sxv, (const float *)model->alpha32, n, F, o0);
+                             ntiles, clist, cidx, spid, xk, (const float *)model->alpha32, n, F, o0);
       }
     }
   }
