@@ -210,11 +210,12 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 // touches (and the two rows a 16-lane store touches) hit distinct banks.
 __device__ __forceinline__ int lds_col(int row, int col) { return (((col >> 3) ^ ((row >> 1) & 7)) << 3) | (col & 7); }
 
-// P 16-byte pieces per thread of a ROWS x 64 operand tile; KC as in stage().
-// Rows at or past R and k at or past kend read as zero.  Row strides are
-// multiples of 8 elements that cover the stored width, so a piece read from
-// a clamped address stays inside its row; nv[j] counts its valid elements
-// and put_tile() masks off the rest once the load has landed.
+// ROWS / 32 16-byte pieces per thread of a ROWS x 64 operand tile; KC as in
+// stage().  Rows at or past R and k at or past kend read as zero.  Row
+// strides are multiples of 8 elements that cover the stored width, so
+// fetch_tile() reads every piece from a clamped address inside its row;
+// piece_valid() counts the piece's valid elements and put_tile() masks off
+// the rest once the load has landed.
 template <int KC, int ROWS>
 __device__ __forceinline__ int piece_valid(int c, int r0, int k0, int R, int kend) {
   constexpr int PK = ROWS / 8;  // pieces per k when rows are contiguous
