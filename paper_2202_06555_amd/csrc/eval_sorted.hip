@@ -50,7 +50,7 @@ constexpr int TPTS = 64;  // points per sub-tile (one MFMA row group per 16)
 #define HDMR_TR_MIXED 64
 #endif
 #ifndef HDMR_TILE_GRID
-#define HDMR_TILE_GRID 4096
+#define HDMR_TILE_GRID 16384
 #endif
 constexpr int TR_FP64 = HDMR_TR_FP64;    // rows per batch, FP64 contraction (one output
                                          // read-modify-write per batch: wide batches pay)
@@ -58,7 +58,7 @@ constexpr int TR_GRAD = HDMR_TR_GRAD;    // rows per batch with the derivative c
 constexpr int TR_MIXED = HDMR_TR_MIXED;  // rows per batch, mixed contraction
 constexpr int TR_FP64_ALT = 32;          // the alternative row batches an autotuner may pick
 constexpr int TR_MIXED_ALT = 32;
-constexpr int TILE_GRID = HDMR_TILE_GRID;  // workgroups of a contraction launch
+constexpr int TILE_GRID = HDMR_TILE_GRID;  // most workgroups of a contraction launch
 constexpr int CHUNK = HDMR_CHUNK;          // points per work item (<= 4 sub-tiles)
 
 __global__ void k_transpose(const double *__restrict__ X, int64_t n, int d, double *__restrict__ XT,
@@ -831,6 +831,10 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
     return rc;
   }
   const unsigned gs = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+  // contraction workgroups: about one per work item (items hold <= CHUNK
+  // points of one cell), within [1024, TILE_GRID]; each walks the items
+  // with a stride of the grid
+  const unsigned tgrid = (unsigned)std::max<int64_t>(1024, std::min<int64_t>((n + CHUNK - 1) / CHUNK, TILE_GRID));
   hipLaunchKernelGGL(k_fill_u8, dim3(gs), dim3(256), 0, stream, nanflag, n);
   hipLaunchKernelGGL(k_transpose, dim3((unsigned)((n + 31) / 32), (unsigned)((d + 31) / 32)), dim3(256), 0, stream,
                      X, n, d, xt, nanflag);
@@ -871,22 +875,22 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
       StageTimer tm(STAGE_CONTRACT, stream);
       for (int o0 = 0; o0 < m; o0 += 64) {
         if (G)
-          hipLaunchKernelGGL((k_tile_fp64<TR_GRAD, true>), dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles,
+          hipLaunchKernelGGL((k_tile_fp64<TR_GRAD, true>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles, ntiles,
                              clist, cidx, spid, xk, n, F, o0, G);
         else if (precision == HDMR_PLAIN_FP64 && variant == 0)
-          hipLaunchKernelGGL((k_tile_fp64<TR_FP64, false>), dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles,
+          hipLaunchKernelGGL((k_tile_fp64<TR_FP64, false>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles, ntiles,
                              clist, cidx, spid, xk, n, F, o0, (double *)nullptr);
         else if (precision == HDMR_PLAIN_FP64)
-          hipLaunchKernelGGL((k_tile_fp64<TR_FP64_ALT, false>), dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles,
+          hipLaunchKernelGGL((k_tile_fp64<TR_FP64_ALT, false>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles,
                              ntiles, clist, cidx, spid, xk, n, F, o0, (double *)nullptr);
         else if (split2)
-          hipLaunchKernelGGL((k_tile_mixed<TR_MIXED, 2>), dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles,
+          hipLaunchKernelGGL((k_tile_mixed<TR_MIXED, 2>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles, ntiles,
                              clist, cidx, spid, xk, (const float *)model->alpha32, n, F, o0);
         else if (variant == 0)
-          hipLaunchKernelGGL((k_tile_mixed<TR_MIXED, 3>), dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles, ntiles,
+          hipLaunchKernelGGL((k_tile_mixed<TR_MIXED, 3>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles, ntiles,
                              clist, cidx, spid, xk, (const float *)model->alpha32, n, F, o0);
         else
-          hipLaunchKernelGGL((k_tile_mixed<TR_MIXED_ALT, 3>), dim3(TILE_GRID), dim3(256), 0, stream, M, P, tiles,
+          hipLaunchKernelGGL((k_tile_mixed<TR_MIXED_ALT, 3>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles,
                              ntiles, clist, cidx, spid, xk, (const float *)model->alpha32, n, F, o0);
       }
     }
