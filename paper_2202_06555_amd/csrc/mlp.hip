@@ -588,6 +588,13 @@ __global__ void k_maxerr(const double *__restrict__ A, const double *__restrict_
 
 unsigned grid_of(int64_t total) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 16384)); }
 // workgroups for one-wave-per-row kernels (4 rows per workgroup of 256)
+// K slices of the out x in weight gradient: enough 64 x 64 tiles for
+// DW_BLOCKS workgroups, at most DW_SPLIT_MAX slices.
+int64_t dw_split(int64_t out, int64_t in) {
+  const int64_t tiles = ((out + TM - 1) / TM) * ((in + TN - 1) / TN);
+  return std::min<int64_t>(DW_SPLIT_MAX, std::max<int64_t>(1, (DW_BLOCKS + tiles - 1) / tiles));
+}
+
 unsigned row_grid(int64_t rows) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((rows + 3) / 4, 16384)); }
 
 template <int TA, int TB, int EPI>
@@ -715,8 +722,7 @@ struct mlp_model {
       dw.N = in[l];
       dw.K = (int)rows;
       // split K so that the (out x in) tile grid fills the chip; slices go to ws
-      const int64_t tiles = ((out[l] + TM - 1) / TM) * ((in[l] + TN - 1) / TN);
-      const int64_t want = std::min<int64_t>(DW_SPLIT_MAX, std::max<int64_t>(1, (DW_BLOCKS + tiles - 1) / tiles));
+      const int64_t want = dw_split(out[l], in[l]);
       dw.kslice = (int)(((rows + want - 1) / want + TK - 1) / TK * TK);
       const int slices = (int)((rows + dw.kslice - 1) / dw.kslice);
       const int64_t len = (int64_t)out[l] * in[l];
@@ -870,8 +876,13 @@ int mlp_create(int32_t d, int32_t width, int32_t m, const float *params, mlp_mod
   net->loss_cap = 1;
   for (int l = 0; l < NL && e == hipSuccess; ++l)
     e = hipMalloc((void **)&net->wb[l], sizeof(bf16) * net->out[l] * net->ldin[l]);
+  // only layers whose weight gradient is split need slices (wide layers fill
+  // the chip unsplit)
   int64_t wsl = (int64_t)COLSUM_CHUNKS * std::max(width, m);
-  for (int l = 0; l < NL; ++l) wsl = std::max<int64_t>(wsl, (int64_t)DW_SPLIT_MAX * net->out[l] * net->in[l]);
+  for (int l = 0; l < NL; ++l) {
+    const int64_t want = dw_split(net->out[l], net->in[l]);
+    if (want > 1) wsl = std::max<int64_t>(wsl, want * net->out[l] * net->in[l]);
+  }
   if (e == hipSuccess) e = hipMalloc((void **)&net->ws, sizeof(float) * wsl);
   net->ws_len = wsl;
   if (e == hipSuccess) e = hipMemcpy(net->p, params, sizeof(float) * o, hipMemcpyHostToDevice);
