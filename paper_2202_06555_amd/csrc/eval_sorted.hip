@@ -41,7 +41,7 @@ constexpr int TPTS = 64;  // points per sub-tile (one MFMA row group per 16)
 #define HDMR_TR_FP64 64
 #endif
 #ifndef HDMR_TR_GRAD
-#define HDMR_TR_GRAD 48
+#define HDMR_TR_GRAD 56
 #endif
 #ifndef HDMR_CHUNK
 #define HDMR_CHUNK 256
