@@ -434,10 +434,30 @@ __device__ __forceinline__ uint4 tile_rec(const uint4 *__restrict__ tiles, int64
 // (group mt, register i) belongs to point mt * 16 + r0 + i * rs of the
 // sub-tile and output col; point p's row starts at F + p * m.  Plain loads and stores: within a pass each
 // (point, output) has exactly one writer and passes are separate launches in
-// stream order.  Two halves of 8 loads keep the live registers bounded.
-template <typename V, typename S>
+// stream order.  The access is latency bound: ALL16 has all 16 loads in
+// flight at once (the mixed kernel, which has the registers); otherwise two
+// halves of 8 loads keep the live registers bounded.
+template <bool ALL16 = false, typename V, typename S>
 __device__ __forceinline__ void add_rows(double *__restrict__ F, const int32_t *pid, S m, int col, int cnt, int r0,
                                          int rs, const V (&acc)[4]) {
+  if constexpr (ALL16) {
+    double f[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int pt = a * 16 + r0 + i * rs;
+        f[a][i] = pt < cnt ? F[(int64_t)pid[pt] * m + col] : 0.0;
+      }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int pt = a * 16 + r0 + i * rs;
+        if (pt < cnt) F[(int64_t)pid[pt] * m + col] = f[a][i] + (double)acc[a][i];
+      }
+    return;
+  }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     double f[2][4];
@@ -761,7 +781,7 @@ __global__ __launch_bounds__(256, 3) void k_tile_mixed(ModelView M, Pass P, cons
             }
           }
           // lane holds rows 4 kg + i of each 16-point group, column jj
-          if (col < m) add_rows(F, SP.pid, m, col, cnt, 4 * kg, 1, acc);
+          if (col < m) add_rows<true>(F, SP.pid, m, col, cnt, 4 * kg, 1, acc);
         }
         pb ^= 1;
       }
