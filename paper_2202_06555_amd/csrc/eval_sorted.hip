@@ -7,18 +7,20 @@
 // small dense product W (points x rows) * A (rows x outputs).  Per pass (one
 // component of the largest order plus the lower-order components inside its
 // dimensions):
-//   keys     : the cell of every point in the key dimensions (<= 16 bits);
+//   keys     : the cell of every point in the key dimensions (<= 16 bits),
+//              and the point's key coordinates interleaved per point;
 //   sort     : radix sort of (key, point) pairs, so the points of a cell are
 //              neighbours; cell bounds;
 //   rows     : the rows of every nonempty cell through the directory
 //              (count, exclusive scan, write: a CSR of (cell, row)); work
 //              items of <= 256 points of one cell;
-//   contract : a workgroup per work item stages the cell's rows and the
-//              surplus operands once, then per 64-point sub-tile forms the
-//              basis weights W = w_S prod phi (eq (3.1), eq (3.2)) in LDS and
-//              multiplies W by the surplus rows on the matrix cores; the
-//              per-point sums are added to the FP64 output rows, which start
-//              at c0.
+//   contract : a workgroup takes work items in turn (a grid of about one
+//              workgroup per item), stages the cell's rows and the surplus
+//              operands once per row batch, then per 64-point sub-tile reads
+//              its points' coordinates by point id, forms the basis weights
+//              W = w_S prod phi (eq (3.1), eq (3.2)) in LDS and multiplies W
+//              by the surplus rows on the matrix cores; the per-point sums
+//              are added to the FP64 output rows, which start at c0.
 // Plain: FP64 weights and surpluses, FP64 MFMA, FP64 accumulation.  Mixed:
 // FP32 weights and surpluses split into three BF16 terms, BF16 MFMA with FP32
 // accumulation per pass, FP64 accumulation across passes and of c0.
