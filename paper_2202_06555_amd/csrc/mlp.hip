@@ -31,10 +31,6 @@ constexpr int WIDE128_MIN_TILES = 1024;  // workgroups of the 128 x 128 tile ker
 
 inline int64_t pad8(int64_t x) { return (x + 7) & ~(int64_t)7; }
 
-#ifndef GELU_FAST
-#define GELU_FAST 1
-#endif
-#if GELU_FAST
 // GELU(z) = 0.5 z (1 + erf(z / sqrt 2)) = 0.5 (z + |z| erf(|z| / sqrt 2)),
 // with erf on [0, inf) by Abramowitz & Stegun 7.1.26 (|error| <= 1.5e-7,
 // far below one BF16 ulp of the stored activation): branch-free, one
@@ -47,9 +43,6 @@ __device__ __forceinline__ float gelu_f(float z) {
   const float erf_abs = fmaf(-poly, __builtin_amdgcn_exp2f(-x * x * 1.4426950408889634f), 1.0f);
   return 0.5f * fmaf(fabsf(z), erf_abs, z);
 }
-#else
-__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
-#endif
 __device__ __forceinline__ float gelu_grad_f(float z) {
   return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
 }
