@@ -480,12 +480,33 @@ __device__ __forceinline__ void add_rows(double *__restrict__ F, const int32_t *
   }
 }
 
+// One 16-point group of a wave's MFMA result added to the outputs (the
+// narrow kernel: lane value i belongs to point p0 + i * rs, output col).
+template <typename S>
+__device__ __forceinline__ void add_group(double *__restrict__ F, const int32_t *pid, S m, int col, int cnt, int p0,
+                                          int rs, const v4d &acc) {
+  double f[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int pt = p0 + i * rs;
+    f[i] = pt < cnt ? F[(int64_t)pid[pt] * m + col] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int pt = p0 + i * rs;
+    if (pt < cnt) F[(int64_t)pid[pt] * m + col] = f[i] + acc[i];
+  }
+}
+
 // Plain FP64 contraction: FP64 weights in LDS (MFMA A operand, shared by the
 // waves), FP64 surplus operands (B) in registers, FP64 MFMA 16x16x4.  With
 // GRAD, every sub-tile step also forms the derivative weights of each key
 // dimension q (row_dweight) and adds their products with the same surplus
 // operands to the gradient rows G + p * d m + dims[q] m (G: n x d x m).
-template <int TR, bool GRAD>
+// NARROW (m <= 16, one output tile): wave w takes the 16-point group w of
+// every sub-tile instead of output tile w of all 64 points, so all four
+// waves share the MFMAs and the read-modify-writes.
+template <int TR, bool GRAD, bool NARROW>
 __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const uint4 *__restrict__ tiles,
                                                       const uint32_t *__restrict__ ntiles_p,
                                                       const CellRow *__restrict__ list, const uint4 *__restrict__ idx,
@@ -499,8 +520,8 @@ __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const
   const int t = threadIdx.x, lane = t & (WAVE - 1), wid = t / WAVE;
   const int kk = lane >> 4, jj = lane & 15;
   const int m = M.m;
-  const int col = o0 + wid * 16 + jj;
-  const bool wave_on = o0 + wid * 16 < m;
+  const int col = NARROW ? o0 + jj : o0 + wid * 16 + jj;
+  const bool wave_on = NARROW || o0 + wid * 16 < m;
   const int64_t ntiles = *ntiles_p;
   if (ntiles == 0) return;
   int64_t it = blockIdx.x;
@@ -582,7 +603,14 @@ __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const
         v4d acc[4];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) acc[mt] = v4d{0.0, 0.0, 0.0, 0.0};
-        if (wave_on) {
+        if constexpr (NARROW) {
+#pragma unroll
+          for (int j = 0; j < TR / 4; ++j)
+            if (4 * j < Rp)
+              acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[wid * 16 + jj][4 * j + kk], b[j], acc[0], 0, 0, 0);
+          // lane holds rows kk + 4 i of the wave's 16-point group, column jj
+          if (col < m) add_group(F, SP.pid, m, col, cnt, wid * 16 + kk, 4, acc[0]);
+        } else if (wave_on) {
 #pragma unroll
           for (int j = 0; j < TR / 4; ++j) {
             if (4 * j < Rp) {
@@ -611,7 +639,14 @@ __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const
             __syncthreads();
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) acc[mt] = v4d{0.0, 0.0, 0.0, 0.0};
-            if (wave_on) {
+            if constexpr (NARROW) {
+#pragma unroll
+              for (int j = 0; j < TR / 4; ++j)
+                if (4 * j < Rp)
+                  acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[wid * 16 + jj][4 * j + kk], b[j], acc[0], 0, 0, 0);
+              if (col < m)
+                add_group(G + (int64_t)P.dims[q] * m, SP.pid, (int64_t)M.d * m, col, cnt, wid * 16 + kk, 4, acc[0]);
+            } else if (wave_on) {
 #pragma unroll
               for (int j = 0; j < TR / 4; ++j) {
                 if (4 * j < Rp) {
@@ -895,15 +930,25 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
     }
     {
       StageTimer tm(STAGE_CONTRACT, stream);
+      const bool narrow = m <= 16;  // one output tile: the waves split the points instead
       for (int o0 = 0; o0 < m; o0 += 64) {
-        if (G)
-          hipLaunchKernelGGL((k_tile_fp64<TR_GRAD, true>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles, ntiles,
-                             clist, cidx, spid, xk, n, F, o0, G);
+        if (G && narrow)
+          hipLaunchKernelGGL((k_tile_fp64<TR_GRAD, true, true>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles,
+                             ntiles, clist, cidx, spid, xk, n, F, o0, G);
+        else if (G)
+          hipLaunchKernelGGL((k_tile_fp64<TR_GRAD, true, false>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles,
+                             ntiles, clist, cidx, spid, xk, n, F, o0, G);
+        else if (precision == HDMR_PLAIN_FP64 && variant == 0 && narrow)
+          hipLaunchKernelGGL((k_tile_fp64<TR_FP64, false, true>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles,
+                             ntiles, clist, cidx, spid, xk, n, F, o0, (double *)nullptr);
         else if (precision == HDMR_PLAIN_FP64 && variant == 0)
-          hipLaunchKernelGGL((k_tile_fp64<TR_FP64, false>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles, ntiles,
-                             clist, cidx, spid, xk, n, F, o0, (double *)nullptr);
+          hipLaunchKernelGGL((k_tile_fp64<TR_FP64, false, false>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles,
+                             ntiles, clist, cidx, spid, xk, n, F, o0, (double *)nullptr);
+        else if (precision == HDMR_PLAIN_FP64 && narrow)
+          hipLaunchKernelGGL((k_tile_fp64<TR_FP64_ALT, false, true>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles,
+                             ntiles, clist, cidx, spid, xk, n, F, o0, (double *)nullptr);
         else if (precision == HDMR_PLAIN_FP64)
-          hipLaunchKernelGGL((k_tile_fp64<TR_FP64_ALT, false>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles,
+          hipLaunchKernelGGL((k_tile_fp64<TR_FP64_ALT, false, false>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles,
                              ntiles, clist, cidx, spid, xk, n, F, o0, (double *)nullptr);
         else if (split2)
           hipLaunchKernelGGL((k_tile_mixed<TR_MIXED, 2>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles, ntiles,
