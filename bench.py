@@ -37,6 +37,7 @@ BF16_PEAK = 2.5e15       # MI355X dense BF16 matrix FLOP/s
 HBM_PEAK = 8.0e12        # MI355X HBM3E bytes/s
 
 KERNEL = {"plain": "k_tile_fp64", "mixed": "k_tile_mixed"}
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def log(msg):
@@ -52,7 +53,7 @@ def _measured_traffic(kernel, workload):
     """HBM bytes per launch of the contraction kernel from the committed
     counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when
     there is none or the kernel source changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.md" % (kernel, workload))
+    path = os.path.join(PROFILES, "%s_%s_traffic.md" % (kernel, workload))
     if not os.path.exists(path):
         return None
     txt = open(path).read()

@@ -12,6 +12,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhdmr.so")
+CEILINGS = os.path.join(PKG, "bench_ceilings")
 
 ARCH = os.environ.get("HDMR_OFFLOAD_ARCH", "gfx950")
 
@@ -49,7 +50,19 @@ def build(jobs: int = 8) -> str:
     if res.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (res.stdout, res.stderr))
     os.replace(tmp, LIB)
+    build_ceilings()
     return LIB
+
+
+def build_ceilings() -> str:
+    """Compile the device-ceiling microbenchmarks (ceilings.hip) into an executable."""
+    tmp = CEILINGS + ".tmp%d" % os.getpid()
+    cmd = [hipcc()] + [f for f in HIPCC_FLAGS if f != "-fPIC"] + [os.path.join(PKG, "ceilings.hip"), "-o", tmp]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed for ceilings.hip:\n%s\n%s" % (res.stdout, res.stderr))
+    os.replace(tmp, CEILINGS)
+    return CEILINGS
 
 
 if __name__ == "__main__":

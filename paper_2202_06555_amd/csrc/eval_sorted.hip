@@ -27,8 +27,12 @@
 // Before the passes the points are transposed to dimension-major order (a
 // pass reads only its key columns) and NaN points are flagged; after them
 // flagged points get NaN outputs.
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
 
 #include <hipcub/hipcub.hpp>
 
@@ -124,11 +128,6 @@ __global__ void k_zero_f64(double *__restrict__ a, int64_t n) {
     a[i] = 0.0;
 }
 
-__global__ void k_write_c0(double *__restrict__ F, const double *__restrict__ c0, int64_t n, int m) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * m; i += (int64_t)gridDim.x * blockDim.x)
-    F[i] = c0[i % m];
-}
-
 __global__ void k_nan_fix(double *__restrict__ F, const uint8_t *__restrict__ nanflag, int64_t n, int m) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * m; e += (int64_t)gridDim.x * blockDim.x)
     if (nanflag[e / m]) F[e] = __builtin_nan("");
@@ -168,14 +167,15 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// A row of a cell as the contraction needs it (32 bytes).
+// A row of a cell as the contraction needs it (32 bytes).  w is the
+// component weight w_S in FP64, as the model stores it.
 struct alignas(16) CellRow {
+  double w;
   int32_t row;
-  float w;          // w_S (exact: 1 or an integer of eq (4.2))
   uint8_t k, pad0, pad1, pad2;
   uint8_t pos[KMAX];
   uint8_t lv[KMAX];
-  uint16_t ixs[KMAX]; // unused padding keeps 16-byte alignment
+  uint32_t pad3[2];
 };
 
 // Discovery of the rows of every nonempty cell of a pass: one wavefront per
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(256) void k_cell_rows(ModelView M, Pass P, const Pa
           {
             CellRow R{};
             R.row = row;
-            R.w = (float)T.w;
+            R.w = T.w;
             R.k = T.k;
             uint4 ix;
 #pragma unroll
@@ -277,9 +277,6 @@ __global__ __launch_bounds__(256) void k_cell_rows(ModelView M, Pass P, const Pa
   }
 }
 
-// Basis weight of a point (coordinates xs[pos]) for one stored row:
-// w_S prod_q max(0, 1 - |x 2^l - i|) (eq (3.1), eq (3.2)); x 2^l - i is exact
-// in FP64.
 // Basis weight of a point with key coordinates x0..x3 for one stored row:
 // w_S prod_q max(0, 1 - |x 2^l - i|) (eq (3.1), eq (3.2)); x 2^l - i is exact
 // in FP64.  (Scalar arguments: a selected element of a local array would be
@@ -287,7 +284,7 @@ __global__ __launch_bounds__(256) void k_cell_rows(ModelView M, Pass P, const Pa
 __device__ __forceinline__ double row_weight(const CellRow &R, const uint4 &ix, double x0, double x1, double x2,
                                              double x3) {
   const uint32_t iv[KMAX] = {ix.x, ix.y, ix.z, ix.w};
-  double w = (double)R.w;
+  double w = R.w;
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) {
     if (q < R.k) {
@@ -311,7 +308,7 @@ __device__ __forceinline__ double row_weight(const CellRow &R, const uint4 &ix, 
 __device__ __forceinline__ double row_dweight(const CellRow &R, const uint4 &ix, double x0, double x1, double x2,
                                               double x3, int qpos) {
   const uint32_t iv[KMAX] = {ix.x, ix.y, ix.z, ix.w};
-  double w = (double)R.w;
+  double w = R.w;
   bool has = false;
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) {
@@ -428,38 +425,90 @@ __device__ __forceinline__ uint4 tile_rec(const uint4 *__restrict__ tiles, int64
 // are loaded into registers at the start of a step and parked in the second
 // LDS buffer before the step's MFMA phase.  Each step:
 //   sync; [batch start: stage the batch's rows, load the wave's surplus
-//   operands]; form the weights of the sub-tile into LDS; sync; MFMA;
-//   add the sums to the outputs (which start at c0).
+//   operands]; form the weights of the sub-tile into LDS; sync; MFMA; sync;
+//   the waves park their sums in LDS (over the weights); sync; the whole
+//   workgroup adds them to the points' accumulator rows, row by row in
+//   16-byte pieces.
 // Wave w owns the 16 outputs o0 + 16 w ...
+//
+// Accumulators: one row of AS values per point (AS = m rounded up to a
+// multiple of 16, rows 128-byte aligned), so a point's 16-output slice is
+// whole cache lines.  Within a pass each (point, output) has exactly one
+// writer and passes are stream-ordered launches, so plain loads and stores
+// suffice.
 
-// Adds a wave's MFMA result for one sub-tile to the outputs: lane value
-// (group mt, register i) belongs to point mt * 16 + r0 + i * rs of the
-// sub-tile and output col; point p's row starts at F + p * m.  Plain loads and stores: within a pass each
-// (point, output) has exactly one writer and passes are separate launches in
-// stream order.  The access is latency bound: ALL16 has all 16 loads in
-// flight at once (the mixed kernel, which has the registers); otherwise two
-// halves of 8 loads keep the live registers bounded.
-template <bool ALL16 = false, typename V, typename S>
+constexpr int OS64 = 66;  // parked FP64 sums: row stride (doubles)
+constexpr int OS32 = 68;  // parked FP32 sums: row stride (floats)
+
+// Adds the parked sums of a sub-tile (s_o[pt * OS64 + c], c < ncols) to the
+// FP64 accumulator rows acc + pid[pt] * AS + o0: 16-byte pieces, all loads of
+// a thread in flight before its stores.  NARROW: ncols == 16.
+template <bool NARROW>
+__device__ __forceinline__ void add_parked_f64(double *__restrict__ acc, int AS, int o0, int ncols,
+                                               const int32_t *pid, int cnt, const double *s_o, int t) {
+  constexpr int CP = NARROW ? 8 : 32;        // column pairs per row a thread row covers
+  constexpr int PR = 256 / CP;               // points per round
+  constexpr int NI = TPTS / PR;              // rounds
+  const int c2 = t % CP, pr = t / CP;
+  const bool col_on = 2 * c2 < ncols;
+  double *base = acc + o0 + 2 * c2;
+  double2 v[NI];
+  int32_t p[NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int pt = pr + PR * i;
+    p[i] = (col_on && pt < cnt) ? pid[pt] : -1;
+    v[i] = p[i] >= 0 ? *reinterpret_cast<const double2 *>(base + (int64_t)p[i] * AS) : make_double2(0.0, 0.0);
+  }
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int pt = pr + PR * i;
+    if (p[i] >= 0) {
+      double2 r = v[i];
+      r.x += s_o[pt * OS64 + 2 * c2];
+      r.y += s_o[pt * OS64 + 2 * c2 + 1];
+      *reinterpret_cast<double2 *>(base + (int64_t)p[i] * AS) = r;
+    }
+  }
+}
+
+// The same for FP32 accumulators (float4 pieces, ncols <= 64).
+__device__ __forceinline__ void add_parked_f32(float *__restrict__ acc, int AS, int o0, int ncols, const int32_t *pid,
+                                               int cnt, const float *s_o, int t) {
+  constexpr int CQ = 16, PR = 256 / CQ, NI = TPTS / PR;
+  const int c4 = t % CQ, pr = t / CQ;
+  const bool col_on = 4 * c4 < ncols;
+  float *base = acc + o0 + 4 * c4;
+  float4 v[NI];
+  int32_t p[NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int pt = pr + PR * i;
+    p[i] = (col_on && pt < cnt) ? pid[pt] : -1;
+    v[i] = p[i] >= 0 ? *reinterpret_cast<const float4 *>(base + (int64_t)p[i] * AS) : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int pt = pr + PR * i;
+    if (p[i] >= 0) {
+      const float *o = s_o + pt * OS32 + 4 * c4;
+      float4 r = v[i];
+      r.x += o[0];
+      r.y += o[1];
+      r.z += o[2];
+      r.w += o[3];
+      *reinterpret_cast<float4 *>(base + (int64_t)p[i] * AS) = r;
+    }
+  }
+}
+
+// Adds a wave's MFMA result for one sub-tile straight to caller-layout rows
+// (the gradient: lane value (group mt, register i) belongs to point
+// mt * 16 + r0 + i * rs of the sub-tile and output col; point p's row starts
+// at F + p * m).  Two halves of 8 loads keep the live registers bounded.
+template <typename V, typename S>
 __device__ __forceinline__ void add_rows(double *__restrict__ F, const int32_t *pid, S m, int col, int cnt, int r0,
                                          int rs, const V (&acc)[4]) {
-  if constexpr (ALL16) {
-    double f[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int pt = a * 16 + r0 + i * rs;
-        f[a][i] = pt < cnt ? F[(int64_t)pid[pt] * m + col] : 0.0;
-      }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int pt = a * 16 + r0 + i * rs;
-        if (pt < cnt) F[(int64_t)pid[pt] * m + col] = f[a][i] + (double)acc[a][i];
-      }
-    return;
-  }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     double f[2][4];
@@ -480,8 +529,8 @@ __device__ __forceinline__ void add_rows(double *__restrict__ F, const int32_t *
   }
 }
 
-// One 16-point group of a wave's MFMA result added to the outputs (the
-// narrow kernel: lane value i belongs to point p0 + i * rs, output col).
+// One 16-point group of a wave's MFMA result added to caller-layout rows
+// (the narrow gradient: lane value i belongs to point p0 + i * rs, output col).
 template <typename S>
 __device__ __forceinline__ void add_group(double *__restrict__ F, const int32_t *pid, S m, int col, int cnt, int p0,
                                           int rs, const v4d &acc) {
@@ -499,29 +548,32 @@ __device__ __forceinline__ void add_group(double *__restrict__ F, const int32_t 
 }
 
 // Plain FP64 contraction: FP64 weights in LDS (MFMA A operand, shared by the
-// waves), FP64 surplus operands (B) in registers, FP64 MFMA 16x16x4.  With
-// GRAD, every sub-tile step also forms the derivative weights of each key
-// dimension q (row_dweight) and adds their products with the same surplus
-// operands to the gradient rows G + p * d m + dims[q] m (G: n x d x m).
+// waves), FP64 surplus operands (B) in registers, FP64 MFMA 16x16x4, sums
+// added to the FP64 accumulator rows (acc, stride AS).  With GRAD, every
+// sub-tile step also forms the derivative weights of each key dimension q
+// (row_dweight) and adds their products with the same surplus operands to
+// the gradient rows G + p * d m + dims[q] m (G: n x d x m).
 // NARROW (m <= 16, one output tile): wave w takes the 16-point group w of
 // every sub-tile instead of output tile w of all 64 points, so all four
-// waves share the MFMAs and the read-modify-writes.
+// waves share the MFMAs.
 template <int TR, bool GRAD, bool NARROW>
 __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const uint4 *__restrict__ tiles,
                                                       const uint32_t *__restrict__ ntiles_p,
                                                       const CellRow *__restrict__ list, const uint4 *__restrict__ idx,
                                                       const int32_t *__restrict__ spid, const double *__restrict__ xk,
-                                                      int64_t n, double *__restrict__ F, int o0,
+                                                      int64_t n, double *__restrict__ acc, int AS, int o0,
                                                       double *__restrict__ G) {
   constexpr int WS = TR + 4;  // W row stride (doubles): spreads A-operand reads over the LDS banks
-  __shared__ double s_w[TPTS][WS];
+  constexpr int SWN = (TPTS * WS > TPTS * OS64) ? TPTS * WS : TPTS * OS64;
+  __shared__ double s_w[SWN];  // weights [TPTS][WS], then the parked sums [TPTS][OS64]
   __shared__ RowsLds<TR> s_rows[2];
   __shared__ PtsLds s_pts[2];
   const int t = threadIdx.x, lane = t & (WAVE - 1), wid = t / WAVE;
   const int kk = lane >> 4, jj = lane & 15;
   const int m = M.m;
   const int col = NARROW ? o0 + jj : o0 + wid * 16 + jj;
-  const bool wave_on = NARROW || o0 + wid * 16 < m;
+  const int ncols = min(NARROW ? 16 : 64, AS - o0);
+  const bool wave_on = NARROW || wid * 16 < ncols;
   const int64_t ntiles = *ntiles_p;
   if (ntiles == 0) return;
   int64_t it = blockIdx.x;
@@ -595,68 +647,84 @@ __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const
           const double x0 = SP.xs[pt][0], x1 = SP.xs[pt][1], x2 = SP.xs[pt][2], x3 = SP.xs[pt][3];
 #pragma unroll 2
           for (int r = grp; r < Rp; r += 4)
-            s_w[pt][r] = (r < Rb && pt < cnt) ? row_weight(SR.rows[r], SR.ix[r], x0, x1, x2, x3) : 0.0;
+            s_w[pt * WS + r] = (r < Rb && pt < cnt) ? row_weight(SR.rows[r], SR.ix[r], x0, x1, x2, x3) : 0.0;
         }
         store_pts(s_pts[pb ^ 1], pn, t);
         if (last) store_rows<TR>(s_rows[rb ^ 1], rn, t);
         __syncthreads();
-        v4d acc[4];
+        v4d a4[4];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) acc[mt] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int mt = 0; mt < 4; ++mt) a4[mt] = v4d{0.0, 0.0, 0.0, 0.0};
+        // point groups of the sub-tile that hold points (padded points have zero weights)
+        const int ngrp = (cnt + 15) >> 4;
         if constexpr (NARROW) {
+          if (wid < ngrp) {
 #pragma unroll
-          for (int j = 0; j < TR / 4; ++j)
-            if (4 * j < Rp)
-              acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[wid * 16 + jj][4 * j + kk], b[j], acc[0], 0, 0, 0);
-          // lane holds rows kk + 4 i of the wave's 16-point group, column jj
-          if (col < m) add_group(F, SP.pid, m, col, cnt, wid * 16 + kk, 4, acc[0]);
+            for (int j = 0; j < TR / 4; ++j)
+              if (4 * j < Rp)
+                a4[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[(wid * 16 + jj) * WS + 4 * j + kk], b[j], a4[0], 0, 0,
+                                                             0);
+          }
         } else if (wave_on) {
 #pragma unroll
           for (int j = 0; j < TR / 4; ++j) {
             if (4 * j < Rp) {
-              // padded points (pt >= cnt) have zero weights
 #pragma unroll
               for (int mt = 0; mt < 4; ++mt)
-                acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[mt * 16 + jj][4 * j + kk], b[j], acc[mt], 0, 0, 0);
+                a4[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[(mt * 16 + jj) * WS + 4 * j + kk], b[j], a4[mt], 0,
+                                                              0, 0);
               // bound how far A-operand loads are hoisted (register pressure)
               __builtin_amdgcn_sched_barrier(0);
             }
           }
-          // lane holds rows kk + 4 i of each 16-point group, column jj
-          if (col < m) add_rows(F, SP.pid, m, col, cnt, kk, 4, acc);
         }
+        __syncthreads();  // every wave is done reading the weights
+        // park: lane holds rows kk + 4 i of each 16-point group, column jj
+        if constexpr (NARROW) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) s_w[(wid * 16 + kk + 4 * i) * OS64 + jj] = a4[0][i];
+        } else if (wave_on) {
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s_w[(mt * 16 + kk + 4 * i) * OS64 + wid * 16 + jj] = a4[mt][i];
+        }
+        __syncthreads();
+        add_parked_f64<NARROW>(acc, AS, o0, ncols, SP.pid, cnt, s_w, t);
         if constexpr (GRAD) {
           // derivative weights of key dimension q, same surplus operands,
           // added to the gradient rows of that dimension
           for (int q = 0; q < P.k; ++q) {
-            __syncthreads();  // the previous MFMAs are done with s_w
+            __syncthreads();  // the previous MFMAs and the parked sums are done with s_w
             {
               const int pt = t >> 2, grp = t & 3;
               const double x0 = SP.xs[pt][0], x1 = SP.xs[pt][1], x2 = SP.xs[pt][2], x3 = SP.xs[pt][3];
               for (int r = grp; r < Rp; r += 4)
-                s_w[pt][r] = (r < Rb && pt < cnt) ? row_dweight(SR.rows[r], SR.ix[r], x0, x1, x2, x3, q) : 0.0;
+                s_w[pt * WS + r] = (r < Rb && pt < cnt) ? row_dweight(SR.rows[r], SR.ix[r], x0, x1, x2, x3, q) : 0.0;
             }
             __syncthreads();
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) acc[mt] = v4d{0.0, 0.0, 0.0, 0.0};
+            for (int mt = 0; mt < 4; ++mt) a4[mt] = v4d{0.0, 0.0, 0.0, 0.0};
             if constexpr (NARROW) {
 #pragma unroll
               for (int j = 0; j < TR / 4; ++j)
                 if (4 * j < Rp)
-                  acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[wid * 16 + jj][4 * j + kk], b[j], acc[0], 0, 0, 0);
+                  a4[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[(wid * 16 + jj) * WS + 4 * j + kk], b[j], a4[0], 0,
+                                                               0, 0);
               if (col < m)
-                add_group(G + (int64_t)P.dims[q] * m, SP.pid, (int64_t)M.d * m, col, cnt, wid * 16 + kk, 4, acc[0]);
+                add_group(G + (int64_t)P.dims[q] * m, SP.pid, (int64_t)M.d * m, col, cnt, wid * 16 + kk, 4, a4[0]);
             } else if (wave_on) {
 #pragma unroll
               for (int j = 0; j < TR / 4; ++j) {
                 if (4 * j < Rp) {
 #pragma unroll
                   for (int mt = 0; mt < 4; ++mt)
-                    acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[mt * 16 + jj][4 * j + kk], b[j], acc[mt], 0, 0, 0);
+                    a4[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[(mt * 16 + jj) * WS + 4 * j + kk], b[j], a4[mt],
+                                                                  0, 0, 0);
                   __builtin_amdgcn_sched_barrier(0);
                 }
               }
-              if (col < m) add_rows(G + (int64_t)P.dims[q] * m, SP.pid, (int64_t)M.d * m, col, cnt, kk, 4, acc);
+              if (col < m) add_rows(G + (int64_t)P.dims[q] * m, SP.pid, (int64_t)M.d * m, col, cnt, kk, 4, a4);
             }
           }
         }
@@ -683,8 +751,8 @@ __device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &mid, __b
 // 16x16x32 with FP32 accumulation.  SPLIT = 3 keeps the six products hi*hi,
 // hi*mid, mid*hi, hi*lo, mid*mid, lo*hi (the dropped ones are below 2^-24
 // relative); SPLIT = 2 keeps hi*hi, hi*mid, mid*hi (about 2^-16 relative).
-// The per-point FP32 sums are added to the FP64 outputs (c0 and the sum over
-// passes and batches stay FP64).
+// The per-point FP32 sums are added to FP32 accumulator rows (acc32, stride
+// AS), which the host folds into the FP64 accumulators every few passes.
 template <int TR, int SPLIT>
 __global__ __launch_bounds__(256, 3) void k_tile_mixed(ModelView M, Pass P, const uint4 *__restrict__ tiles,
                                                        const uint32_t *__restrict__ ntiles_p,
@@ -693,17 +761,22 @@ __global__ __launch_bounds__(256, 3) void k_tile_mixed(ModelView M, Pass P, cons
                                                        const int32_t *__restrict__ spid,
                                                        const double *__restrict__ xk,
                                                        const float *__restrict__ alpha32, int64_t n,
-                                                       double *__restrict__ F, int o0) {
+                                                       float *__restrict__ acc, int AS, int o0) {
   static_assert(TR % 32 == 0, "rows per batch: a multiple of the MFMA depth");
   constexpr int WS = TR + 8;  // W row stride (bf16), 16-byte aligned rows
-  __shared__ __attribute__((aligned(16))) __bf16 s_w[3][TPTS][WS];
+  constexpr int SWB = 3 * TPTS * WS * 2;   // bytes of the three weight planes
+  constexpr int SOB = TPTS * OS32 * 4;     // bytes of the parked sums
+  __shared__ __attribute__((aligned(16))) char s_raw[SWB > SOB ? SWB : SOB];
+  __bf16 *s_w = reinterpret_cast<__bf16 *>(s_raw);  // [3][TPTS][WS]
+  float *s_o = reinterpret_cast<float *>(s_raw);    // [TPTS][OS32]
   __shared__ RowsLds<TR> s_rows[2];
   __shared__ PtsLds s_pts[2];
   const int t = threadIdx.x, lane = t & (WAVE - 1), wid = t / WAVE;
   const int kg = lane >> 4, jj = lane & 15;
   const int m = M.m;
   const int col = o0 + wid * 16 + jj;
-  const bool wave_on = o0 + wid * 16 < m;
+  const int ncols = min(64, AS - o0);
+  const bool wave_on = wid * 16 < ncols;
   const int64_t ntiles = *ntiles_p;
   if (ntiles == 0) return;
   int64_t it = blockIdx.x;
@@ -781,17 +854,18 @@ __global__ __launch_bounds__(256, 3) void k_tile_mixed(ModelView M, Pass P, cons
             const float v = (r < Rb && pt < cnt) ? (float)row_weight(SR.rows[r], SR.ix[r], x0, x1, x2, x3) : 0.f;
             __bf16 h, md, l;
             split_bf16(v, h, md, l);
-            s_w[0][pt][r] = h;
-            s_w[1][pt][r] = md;
-            s_w[2][pt][r] = l;
+            s_w[(0 * TPTS + pt) * WS + r] = h;
+            s_w[(1 * TPTS + pt) * WS + r] = md;
+            s_w[(2 * TPTS + pt) * WS + r] = l;
           }
         }
         store_pts(s_pts[pb ^ 1], pn, t);
         if (last) store_rows<TR>(s_rows[rb ^ 1], rn, t);
         __syncthreads();
-        v4f acc[4];
+        v4f a4[4];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) acc[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int mt = 0; mt < 4; ++mt) a4[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+        const int ngrp = (cnt + 15) >> 4;
         if (wave_on) {
 #pragma unroll
           for (int st = 0; st < TR / 32; ++st) {
@@ -799,27 +873,37 @@ __global__ __launch_bounds__(256, 3) void k_tile_mixed(ModelView M, Pass P, cons
               // padded points (pt >= cnt) have zero weights
 #pragma unroll
               for (int mt = 0; mt < 4; ++mt) {
-                const int ro = mt * 16 + jj, ko = 32 * st + 8 * kg;
-                const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(&s_w[0][ro][ko]);
-                const bf16x8 am = *reinterpret_cast<const bf16x8 *>(&s_w[1][ro][ko]);
-                v4f c = acc[mt];
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[st], c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[st], c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[st], c, 0, 0, 0);
-                if constexpr (SPLIT > 2) {
-                  const bf16x8 al = *reinterpret_cast<const bf16x8 *>(&s_w[2][ro][ko]);
-                  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[st], c, 0, 0, 0);
-                  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm[st], c, 0, 0, 0);
-                  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[st], c, 0, 0, 0);
+                if (mt < ngrp) {
+                  const int ro = mt * 16 + jj, ko = 32 * st + 8 * kg;
+                  const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(&s_w[(0 * TPTS + ro) * WS + ko]);
+                  const bf16x8 am = *reinterpret_cast<const bf16x8 *>(&s_w[(1 * TPTS + ro) * WS + ko]);
+                  v4f c = a4[mt];
+                  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[st], c, 0, 0, 0);
+                  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[st], c, 0, 0, 0);
+                  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[st], c, 0, 0, 0);
+                  if constexpr (SPLIT > 2) {
+                    const bf16x8 al = *reinterpret_cast<const bf16x8 *>(&s_w[(2 * TPTS + ro) * WS + ko]);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[st], c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm[st], c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[st], c, 0, 0, 0);
+                  }
+                  a4[mt] = c;
                 }
-                acc[mt] = c;
                 __builtin_amdgcn_sched_barrier(0);
               }
             }
           }
-          // lane holds rows 4 kg + i of each 16-point group, column jj
-          if (col < m) add_rows<true>(F, SP.pid, m, col, cnt, 4 * kg, 1, acc);
         }
+        __syncthreads();  // every wave is done reading the weights
+        // park: lane holds rows 4 kg + i of each 16-point group, column jj
+        if (wave_on) {
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s_o[(mt * 16 + 4 * kg + i) * OS32 + wid * 16 + jj] = a4[mt][i];
+        }
+        __syncthreads();
+        add_parked_f32(acc, AS, o0, ncols, SP.pid, cnt, s_o, t);
         pb ^= 1;
       }
     }
@@ -828,21 +912,145 @@ __global__ __launch_bounds__(256, 3) void k_tile_mixed(ModelView M, Pass P, cons
   }
 }
 
-template <typename T>
-int ws_alloc(T **p, size_t count, hipStream_t s) {
-  HDMR_HIP(hipMallocAsync((void **)p, std::max<size_t>(count, 1) * sizeof(T), s));
-  return HDMR_OK;
+// Accumulator rows start at c0 (columns >= m at 0).
+__global__ void k_init_acc(double *__restrict__ acc, const double *__restrict__ c0, int64_t n, int m, int AS) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * AS; e += (int64_t)gridDim.x * blockDim.x) {
+    const int o = (int)(e % AS);
+    acc[e] = o < m ? c0[o] : 0.0;
+  }
+}
+
+__global__ void k_zero_f32(float *__restrict__ a, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = 0.f;
+}
+
+// FP32 partial sums folded into the FP64 accumulators (and cleared).
+__global__ void k_fold(double *__restrict__ acc, float *__restrict__ acc32, int64_t total) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    acc[e] += (double)acc32[e];
+    acc32[e] = 0.f;
+  }
+}
+
+// Caller-layout outputs F (n x m) from the accumulator rows (plus the
+// unfolded FP32 partial sums, if any); points with a NaN coordinate get NaN.
+__global__ void k_finish(double *__restrict__ F, const double *__restrict__ acc, const float *__restrict__ acc32,
+                         const uint8_t *__restrict__ nanflag, int64_t n, int m, int AS) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * m; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e / m;
+    const int o = (int)(e - p * m);
+    double v = acc[p * AS + o];
+    if (acc32) v += (double)acc32[p * AS + o];
+    F[e] = nanflag[p] ? __builtin_nan("") : v;
+  }
+}
+
+// Carves aligned sub-buffers out of one allocation; with base == nullptr it
+// only adds up the size.
+struct Carve {
+  char *base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  T *take(size_t count) {
+    const size_t at = (off + 255) & ~(size_t)255;
+    off = at + std::max<size_t>(count, 1) * sizeof(T);
+    return base ? reinterpret_cast<T *>(base + at) : nullptr;
+  }
+};
+
+// Buffers of one pass in flight (two sets: the keys, sort and row discovery
+// of the next pass run on a second stream while this pass contracts).
+struct PassBufs {
+  uint16_t *key, *key_s;
+  int32_t *idx, *spid;
+  double *xk;
+  uint32_t *bstart, *bend, *ntile, *toff, *ntiles, *crows, *coff;
+  CellRow *clist;
+  uint4 *cidx, *tiles;
+  void *tmp;
+};
+
+struct Workspace {
+  double *xt, *acc;
+  float *acc32;
+  uint8_t *nanflag;
+  PassBufs pb[2];
+  size_t tmp_bytes;
+};
+
+void carve_workspace(Carve &C, Workspace &W, int64_t n, int d, int AS, bool mixed, int64_t list_max, size_t tmp_bytes) {
+  const size_t max_tiles = (size_t)(n / CHUNK) + 65536 + 1;
+  W.xt = C.take<double>((size_t)n * d);
+  W.acc = C.take<double>((size_t)n * AS);
+  W.acc32 = mixed ? C.take<float>((size_t)n * AS) : nullptr;
+  W.nanflag = C.take<uint8_t>((size_t)n);
+  W.tmp_bytes = tmp_bytes;
+  for (PassBufs &B : W.pb) {
+    B.key = C.take<uint16_t>((size_t)n);
+    B.key_s = C.take<uint16_t>((size_t)n);
+    B.idx = C.take<int32_t>((size_t)n);
+    B.spid = C.take<int32_t>((size_t)n);
+    B.xk = C.take<double>((size_t)n * KMAX);
+    B.bstart = C.take<uint32_t>(65536);
+    B.bend = C.take<uint32_t>(65536);
+    B.ntile = C.take<uint32_t>(65536);
+    B.toff = C.take<uint32_t>(65536);
+    B.ntiles = C.take<uint32_t>(1);
+    B.crows = C.take<uint32_t>(65536);
+    B.coff = C.take<uint32_t>(65536);
+    B.clist = C.take<CellRow>((size_t)list_max);
+    B.cidx = C.take<uint4>((size_t)list_max);
+    B.tiles = C.take<uint4>(max_tiles);
+    B.tmp = C.take<char>(tmp_bytes);
+  }
+}
+
+// The second stream of a device (default priority, non-blocking), created
+// once and kept for the life of the process.
+hipStream_t side_stream(int device) {
+  static std::mutex mu;
+  static std::vector<hipStream_t> streams;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)streams.size() <= device) streams.resize((size_t)device + 1, nullptr);
+  if (!streams[(size_t)device]) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    streams[(size_t)device] = s;
+  }
+  return streams[(size_t)device];
 }
 
 }  // namespace
 
+// Size of the evaluation workspace of eval_sorted (bytes).
+int eval_sorted_workspace(const hdmr_model *model, int64_t n, int precision, size_t *bytes) {
+  const int AS = (model->m + 15) & ~15;
+  int64_t list_max = 1;
+  for (const Pass &P : model->passes) list_max = std::max<int64_t>(list_max, P.list_bound);
+  size_t tmp_sort = 0, tmp_scan = 0;
+  if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_sort, (uint16_t *)nullptr, (uint16_t *)nullptr,
+                                         (int32_t *)nullptr, (int32_t *)nullptr, (int)std::max<int64_t>(n, 1), 0, 16,
+                                         (hipStream_t)0) != hipSuccess ||
+      hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_scan, (uint32_t *)nullptr, (uint32_t *)nullptr, 65536,
+                                       (hipStream_t)0) != hipSuccess)
+    return fail(HDMR_EDEVICE, "hipcub temporary storage query failed");
+  Carve C;
+  Workspace W{};
+  carve_workspace(C, W, n, model->d, AS, precision == HDMR_MIXED, list_max, std::max(tmp_sort, tmp_scan));
+  *bytes = C.off + 256;
+  return HDMR_OK;
+}
+
 int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, int precision, hipStream_t stream,
-                int variant, double *G) {
+                int variant, double *G, void *ws_base, size_t ws_bytes) {
   const ModelView M = model->view();
   const int d = M.d, m = M.m;
+  const int AS = (m + 15) & ~15;  // accumulator row stride: whole 16-output slices
   if (n >= (int64_t)INT32_MAX) return fail(HDMR_EUNSUPPORTED, "n >= 2^31 points in one call");
   if (precision == HDMR_MIXED && !model->alpha32) return fail(HDMR_EUNSUPPORTED, "model has no FP32 surpluses");
   if (G && precision != HDMR_PLAIN_FP64) return fail(HDMR_EUNSUPPORTED, "gradients are FP64 only");
+  const bool mixed = precision == HDMR_MIXED;
   // the mixed path keeps three BF16 terms; HDMR_MIXED_SPLIT=2 selects two
   // (about 1e-5 relative: below the 1e-6 bar on the benchmark workloads)
   const char *split_env = std::getenv("HDMR_MIXED_SPLIT");
@@ -850,124 +1058,148 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
   int64_t list_max = 1;
   for (const Pass &P : model->passes) list_max = std::max<int64_t>(list_max, P.list_bound);
   if (list_max >= (int64_t)UINT32_MAX) return fail(HDMR_EUNSUPPORTED, "cell row lists exceed 2^32 entries");
-  double *xt = nullptr;
-  uint8_t *nanflag = nullptr;
-  double *xk = nullptr;
-  uint16_t *key = nullptr, *key_s = nullptr;
-  int32_t *idx = nullptr, *spid = nullptr;
-  uint32_t *bstart = nullptr, *bend = nullptr, *ntile = nullptr, *toff = nullptr, *ntiles = nullptr;
-  uint32_t *crows = nullptr, *coff = nullptr;
-  CellRow *clist = nullptr;
-  uint4 *cidx = nullptr;
-  uint4 *tiles = nullptr;
-  void *tmp = nullptr;
   size_t tmp_sort = 0, tmp_scan = 0;
-  if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_sort, key, key_s, idx, spid, (int)n, 0, 16, stream) !=
-          hipSuccess ||
-      hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_scan, ntile, toff, 65536, stream) != hipSuccess)
+  if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_sort, (uint16_t *)nullptr, (uint16_t *)nullptr,
+                                         (int32_t *)nullptr, (int32_t *)nullptr, (int)n, 0, 16, stream) != hipSuccess ||
+      hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_scan, (uint32_t *)nullptr, (uint32_t *)nullptr, 65536,
+                                       stream) != hipSuccess)
     return fail(HDMR_EDEVICE, "hipcub temporary storage query failed");
-  const size_t max_tiles = (size_t)(n / CHUNK) + 65536 + 1;
   const size_t tmp_bytes = std::max(tmp_sort, tmp_scan);
-  int rc = HDMR_OK;
-  auto release = [&]() {
-    void *ptrs[] = {xt, xk, nanflag, key, key_s, idx, spid, bstart, bend, ntile, toff, ntiles, tiles, tmp,
-                    crows, coff, clist, cidx};
-    for (void *p : ptrs) (void)hipFreeAsync(p, stream);
-  };
-  if ((rc = ws_alloc(&xt, (size_t)n * d, stream)) || (rc = ws_alloc(&nanflag, (size_t)n, stream)) ||
-      (rc = ws_alloc(&xk, (size_t)n * KMAX, stream)) ||
-      (rc = ws_alloc(&key, (size_t)n, stream)) || (rc = ws_alloc(&key_s, (size_t)n, stream)) ||
-      (rc = ws_alloc(&idx, (size_t)n, stream)) || (rc = ws_alloc(&spid, (size_t)n, stream)) ||
-      (rc = ws_alloc(&bstart, (size_t)65536, stream)) || (rc = ws_alloc(&bend, (size_t)65536, stream)) ||
-      (rc = ws_alloc(&ntile, (size_t)65536, stream)) || (rc = ws_alloc(&toff, (size_t)65536, stream)) ||
-      (rc = ws_alloc(&ntiles, (size_t)1, stream)) || (rc = ws_alloc(&tiles, max_tiles, stream)) ||
-      (rc = ws_alloc(&crows, (size_t)65536, stream)) || (rc = ws_alloc(&coff, (size_t)65536, stream)) ||
-      (rc = ws_alloc(&clist, (size_t)list_max, stream)) || (rc = ws_alloc(&cidx, (size_t)list_max, stream)) ||
-      (rc = ws_alloc((char **)&tmp, tmp_bytes, stream))) {
-    release();
-    return rc;
+  Carve C;
+  Workspace W{};
+  carve_workspace(C, W, n, d, AS, mixed, list_max, tmp_bytes);
+  const size_t need = C.off + 256;
+  char *base = nullptr;
+  const bool own = ws_base == nullptr;
+  if (own) {
+    HDMR_HIP(hipMallocAsync((void **)&base, need, stream));
+  } else {
+    if (ws_bytes < need)
+      return fail(HDMR_EINVAL, "workspace of " + std::to_string(ws_bytes) + " bytes is below the " +
+                                   std::to_string(need) + " this evaluation needs");
+    base = reinterpret_cast<char *>(((uintptr_t)ws_base + 255) & ~(uintptr_t)255);
   }
+  C = Carve{};
+  C.base = base;
+  carve_workspace(C, W, n, d, AS, mixed, list_max, tmp_bytes);
+  hipStream_t side = side_stream(model->device);
+  hipEvent_t ev_ready = nullptr, ev_side_end = nullptr, ev_sorted[2] = {nullptr, nullptr},
+             ev_done[2] = {nullptr, nullptr};
+  hipError_t e = side ? hipSuccess : hipErrorInvalidValue;
+  for (hipEvent_t *ev : {&ev_ready, &ev_side_end, &ev_sorted[0], &ev_sorted[1], &ev_done[0], &ev_done[1]})
+    if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
   const unsigned gs = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
   // contraction workgroups: about one per work item (items hold <= CHUNK
   // points of one cell), within [1024, TILE_GRID]; each walks the items
   // with a stride of the grid
   const unsigned tgrid = (unsigned)std::max<int64_t>(1024, std::min<int64_t>((n + CHUNK - 1) / CHUNK, TILE_GRID));
-  hipLaunchKernelGGL(k_fill_u8, dim3(gs), dim3(256), 0, stream, nanflag, n);
-  hipLaunchKernelGGL(k_transpose, dim3((unsigned)((n + 31) / 32), (unsigned)((d + 31) / 32)), dim3(256), 0, stream,
-                     X, n, d, xt, nanflag);
-  hipLaunchKernelGGL(k_write_c0, dim3(gs), dim3(256), 0, stream, F, M.c0, n, m);
-  if (G) hipLaunchKernelGGL(k_zero_f64, dim3(gs), dim3(256), 0, stream, G, n * d * m);
-  hipError_t e = hipSuccess;
-  for (const Pass &P : model->passes) {
+  const unsigned ga = (unsigned)std::min<int64_t>((n * AS + 255) / 256, 65536);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_fill_u8, dim3(gs), dim3(256), 0, stream, W.nanflag, n);
+    hipLaunchKernelGGL(k_transpose, dim3((unsigned)((n + 31) / 32), (unsigned)((d + 31) / 32)), dim3(256), 0, stream,
+                       X, n, d, W.xt, W.nanflag);
+    hipLaunchKernelGGL(k_init_acc, dim3(ga), dim3(256), 0, stream, W.acc, M.c0, n, m, AS);
+    if (mixed) hipLaunchKernelGGL(k_zero_f32, dim3(ga), dim3(256), 0, stream, W.acc32, n * AS);
+    if (G) hipLaunchKernelGGL(k_zero_f64, dim3(gs), dim3(256), 0, stream, G, n * d * m);
+    e = hipEventRecord(ev_ready, stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, ev_ready, 0);
+  }
+  constexpr int FOLD_EVERY = 16;  // passes of FP32 partial sums per fold into FP64
+  int since_fold = 0;
+  for (size_t pi = 0; pi < model->passes.size() && e == hipSuccess; ++pi) {
+    const Pass &P = model->passes[pi];
+    const int bsel = (int)(pi & 1);
+    PassBufs &B = W.pb[bsel];
     const int nbins = 1 << P.key_bits;
     const unsigned gb = (unsigned)((nbins + 255) / 256);
     const unsigned gc = (unsigned)std::min((nbins + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, 8192);
+    // keys, sort and row discovery of this pass on the second stream, once
+    // the contraction two passes back is done with this buffer set
+    if (pi >= 2 && (e = hipStreamWaitEvent(side, ev_done[bsel], 0)) != hipSuccess) break;
     {
-      StageTimer tm(STAGE_SORT, stream);
-      hipLaunchKernelGGL(k_keys, dim3(gs), dim3(256), 0, stream, xt, n, P, key, idx, xk);
+      StageTimer tm(STAGE_SORT, side);
+      hipLaunchKernelGGL(k_keys, dim3(gs), dim3(256), 0, side, W.xt, n, P, B.key, B.idx, B.xk);
       size_t tb = tmp_bytes;
-      e = hipcub::DeviceRadixSort::SortPairs(tmp, tb, key, key_s, idx, spid, (int)n, 0, P.key_bits, stream);
+      e = hipcub::DeviceRadixSort::SortPairs(B.tmp, tb, B.key, B.key_s, B.idx, B.spid, (int)n, 0, P.key_bits, side);
       if (e != hipSuccess) break;
-      hipLaunchKernelGGL(k_fill2_u32, dim3(gb), dim3(256), 0, stream, bstart, bend, (int64_t)nbins);
-      hipLaunchKernelGGL(k_bounds, dim3(gs), dim3(256), 0, stream, key_s, n, bstart, bend);
+      hipLaunchKernelGGL(k_fill2_u32, dim3(gb), dim3(256), 0, side, B.bstart, B.bend, (int64_t)nbins);
+      hipLaunchKernelGGL(k_bounds, dim3(gs), dim3(256), 0, side, B.key_s, n, B.bstart, B.bend);
     }
     {
       // rows of every nonempty cell (count, offsets, write), then the tiles
-      StageTimer tm(STAGE_ROWS, stream);
-      hipLaunchKernelGGL(k_cell_rows, dim3(gc), dim3(256), 0, stream, M, P, model->pass_tups, bstart, bend, nbins,
-                         (const uint32_t *)nullptr, clist, cidx, crows);
+      StageTimer tm(STAGE_ROWS, side);
+      hipLaunchKernelGGL(k_cell_rows, dim3(gc), dim3(256), 0, side, M, P, model->pass_tups, B.bstart, B.bend, nbins,
+                         (const uint32_t *)nullptr, B.clist, B.cidx, B.crows);
       size_t tb = tmp_bytes;
-      e = hipcub::DeviceScan::ExclusiveSum(tmp, tb, crows, coff, nbins, stream);
+      e = hipcub::DeviceScan::ExclusiveSum(B.tmp, tb, B.crows, B.coff, nbins, side);
       if (e != hipSuccess) break;
-      hipLaunchKernelGGL(k_cell_rows, dim3(gc), dim3(256), 0, stream, M, P, model->pass_tups, bstart, bend, nbins,
-                         (const uint32_t *)coff, clist, cidx, crows);
-      hipLaunchKernelGGL(k_tile_counts, dim3(gb), dim3(256), 0, stream, bstart, bend, nbins, ntile);
+      hipLaunchKernelGGL(k_cell_rows, dim3(gc), dim3(256), 0, side, M, P, model->pass_tups, B.bstart, B.bend, nbins,
+                         (const uint32_t *)B.coff, B.clist, B.cidx, B.crows);
+      hipLaunchKernelGGL(k_tile_counts, dim3(gb), dim3(256), 0, side, B.bstart, B.bend, nbins, B.ntile);
       tb = tmp_bytes;
-      e = hipcub::DeviceScan::ExclusiveSum(tmp, tb, ntile, toff, nbins, stream);
+      e = hipcub::DeviceScan::ExclusiveSum(B.tmp, tb, B.ntile, B.toff, nbins, side);
       if (e != hipSuccess) break;
-      hipLaunchKernelGGL(k_write_tiles, dim3(gb), dim3(256), 0, stream, bstart, bend, ntile, toff, crows, coff,
-                         nbins, tiles, ntiles);
+      hipLaunchKernelGGL(k_write_tiles, dim3(gb), dim3(256), 0, side, B.bstart, B.bend, B.ntile, B.toff, B.crows,
+                         B.coff, nbins, B.tiles, B.ntiles);
     }
+    if ((e = hipEventRecord(ev_sorted[bsel], side)) != hipSuccess) break;
+    if ((e = hipStreamWaitEvent(stream, ev_sorted[bsel], 0)) != hipSuccess) break;
     {
       StageTimer tm(STAGE_CONTRACT, stream);
       const bool narrow = m <= 16;  // one output tile: the waves split the points instead
-      for (int o0 = 0; o0 < m; o0 += 64) {
+      for (int o0 = 0; o0 < AS; o0 += 64) {
         if (G && narrow)
-          hipLaunchKernelGGL((k_tile_fp64<TR_GRAD, true, true>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles,
-                             ntiles, clist, cidx, spid, xk, n, F, o0, G);
+          hipLaunchKernelGGL((k_tile_fp64<TR_GRAD, true, true>), dim3(tgrid), dim3(256), 0, stream, M, P, B.tiles,
+                             B.ntiles, B.clist, B.cidx, B.spid, B.xk, n, W.acc, AS, o0, G);
         else if (G)
-          hipLaunchKernelGGL((k_tile_fp64<TR_GRAD, true, false>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles,
-                             ntiles, clist, cidx, spid, xk, n, F, o0, G);
-        else if (precision == HDMR_PLAIN_FP64 && variant == 0 && narrow)
-          hipLaunchKernelGGL((k_tile_fp64<TR_FP64, false, true>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles,
-                             ntiles, clist, cidx, spid, xk, n, F, o0, (double *)nullptr);
-        else if (precision == HDMR_PLAIN_FP64 && variant == 0)
-          hipLaunchKernelGGL((k_tile_fp64<TR_FP64, false, false>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles,
-                             ntiles, clist, cidx, spid, xk, n, F, o0, (double *)nullptr);
-        else if (precision == HDMR_PLAIN_FP64 && narrow)
-          hipLaunchKernelGGL((k_tile_fp64<TR_FP64_ALT, false, true>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles,
-                             ntiles, clist, cidx, spid, xk, n, F, o0, (double *)nullptr);
-        else if (precision == HDMR_PLAIN_FP64)
-          hipLaunchKernelGGL((k_tile_fp64<TR_FP64_ALT, false, false>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles,
-                             ntiles, clist, cidx, spid, xk, n, F, o0, (double *)nullptr);
+          hipLaunchKernelGGL((k_tile_fp64<TR_GRAD, true, false>), dim3(tgrid), dim3(256), 0, stream, M, P, B.tiles,
+                             B.ntiles, B.clist, B.cidx, B.spid, B.xk, n, W.acc, AS, o0, G);
+        else if (!mixed && variant == 0 && narrow)
+          hipLaunchKernelGGL((k_tile_fp64<TR_FP64, false, true>), dim3(tgrid), dim3(256), 0, stream, M, P, B.tiles,
+                             B.ntiles, B.clist, B.cidx, B.spid, B.xk, n, W.acc, AS, o0, (double *)nullptr);
+        else if (!mixed && variant == 0)
+          hipLaunchKernelGGL((k_tile_fp64<TR_FP64, false, false>), dim3(tgrid), dim3(256), 0, stream, M, P, B.tiles,
+                             B.ntiles, B.clist, B.cidx, B.spid, B.xk, n, W.acc, AS, o0, (double *)nullptr);
+        else if (!mixed && narrow)
+          hipLaunchKernelGGL((k_tile_fp64<TR_FP64_ALT, false, true>), dim3(tgrid), dim3(256), 0, stream, M, P,
+                             B.tiles, B.ntiles, B.clist, B.cidx, B.spid, B.xk, n, W.acc, AS, o0, (double *)nullptr);
+        else if (!mixed)
+          hipLaunchKernelGGL((k_tile_fp64<TR_FP64_ALT, false, false>), dim3(tgrid), dim3(256), 0, stream, M, P,
+                             B.tiles, B.ntiles, B.clist, B.cidx, B.spid, B.xk, n, W.acc, AS, o0, (double *)nullptr);
         else if (split2)
-          hipLaunchKernelGGL((k_tile_mixed<TR_MIXED, 2>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles, ntiles,
-                             clist, cidx, spid, xk, (const float *)model->alpha32, n, F, o0);
+          hipLaunchKernelGGL((k_tile_mixed<TR_MIXED, 2>), dim3(tgrid), dim3(256), 0, stream, M, P, B.tiles, B.ntiles,
+                             B.clist, B.cidx, B.spid, B.xk, (const float *)model->alpha32, n, W.acc32, AS, o0);
         else if (variant == 0)
-          hipLaunchKernelGGL((k_tile_mixed<TR_MIXED, 3>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles, ntiles,
-                             clist, cidx, spid, xk, (const float *)model->alpha32, n, F, o0);
+          hipLaunchKernelGGL((k_tile_mixed<TR_MIXED, 3>), dim3(tgrid), dim3(256), 0, stream, M, P, B.tiles, B.ntiles,
+                             B.clist, B.cidx, B.spid, B.xk, (const float *)model->alpha32, n, W.acc32, AS, o0);
         else
-          hipLaunchKernelGGL((k_tile_mixed<TR_MIXED_ALT, 3>), dim3(tgrid), dim3(256), 0, stream, M, P, tiles,
-                             ntiles, clist, cidx, spid, xk, (const float *)model->alpha32, n, F, o0);
+          hipLaunchKernelGGL((k_tile_mixed<TR_MIXED_ALT, 3>), dim3(tgrid), dim3(256), 0, stream, M, P, B.tiles,
+                             B.ntiles, B.clist, B.cidx, B.spid, B.xk, (const float *)model->alpha32, n, W.acc32, AS,
+                             o0);
       }
     }
+    if ((e = hipEventRecord(ev_done[bsel], stream)) != hipSuccess) break;
+    if (mixed && ++since_fold == FOLD_EVERY) {
+      hipLaunchKernelGGL(k_fold, dim3(ga), dim3(256), 0, stream, W.acc, W.acc32, n * AS);
+      since_fold = 0;
+    }
+  }
+  // the second stream's work is done before the workspace goes
+  if (side && ev_side_end) {
+    const hipError_t e2 = hipEventRecord(ev_side_end, side);
+    const hipError_t e3 = e2 == hipSuccess ? hipStreamWaitEvent(stream, ev_side_end, 0) : e2;
+    if (e == hipSuccess) e = e3;
+    if (e3 != hipSuccess) (void)hipStreamSynchronize(side);
   }
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_nan_fix, dim3(gs), dim3(256), 0, stream, F, nanflag, n, m);
-    if (G) hipLaunchKernelGGL(k_nan_fix, dim3(gs), dim3(256), 0, stream, G, nanflag, n, d * m);
+    hipLaunchKernelGGL(k_finish, dim3(gs), dim3(256), 0, stream, F, W.acc, mixed ? W.acc32 : nullptr, W.nanflag, n, m,
+                       AS);
+    if (G) hipLaunchKernelGGL(k_nan_fix, dim3(gs), dim3(256), 0, stream, G, W.nanflag, n, d * m);
     e = hipGetLastError();
   }
-  release();
+  for (hipEvent_t ev : {ev_ready, ev_side_end, ev_sorted[0], ev_sorted[1], ev_done[0], ev_done[1]})
+    if (ev) (void)hipEventDestroy(ev);
+  if (own) (void)hipFreeAsync(base, stream);
   if (e != hipSuccess) return hip_fail(e, "sorted evaluation");
   return HDMR_OK;
 }

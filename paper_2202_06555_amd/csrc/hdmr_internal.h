@@ -146,8 +146,12 @@ void keep_pool_memory(int device);
 // HDMR_MIXED; variant 0 uses the default row batch of the contraction, 1 the
 // smaller alternative.  With G (n x d x m, plain precision only) the
 // gradient is computed as well.
+// ws_base (device, ws_bytes bytes) supplies the workspace; with NULL it is
+// allocated stream-ordered on the device's pool and released at the end.
 int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, int precision, hipStream_t stream,
-                int variant = 0, double *G = nullptr);
+                int variant = 0, double *G = nullptr, void *ws_base = nullptr, size_t ws_bytes = 0);
+// Workspace bytes eval_sorted needs for n points at that precision.
+int eval_sorted_workspace(const hdmr_model *model, int64_t n, int precision, size_t *bytes);
 
 // Drop every cached batched-launch graph that refers to the model (batched.hip).
 void batched_forget(const hdmr_model *model);

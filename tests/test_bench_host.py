@@ -17,10 +17,11 @@ def test_more_than_one_gpu_exits_with_a_message():
 
 def test_traffic_is_reported_only_for_the_profiled_source(tmp_path, monkeypatch):
     import bench
-    for kernel in ("k_tile_fp64", "k_tile_mixed"):
-        t = bench._measured_traffic(kernel, "c3")
-        # the committed summary was taken on the current source
-        assert t is not None and 1e9 < t < 1e10
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
+    h = bench._source_hash()
+    (tmp_path / "k_tile_fp64_c3_traffic.md").write_text(
+        "hbm_bytes_per_launch: 4.5e+09\nsource_sha256: %s\n" % h)
+    assert bench._measured_traffic("k_tile_fp64", "c3") == 4.5e9
     # a different source hash (the kernel changed since) gives no figure
     monkeypatch.setattr(bench, "_source_hash", lambda: "0" * 64)
     assert bench._measured_traffic("k_tile_fp64", "c3") is None
