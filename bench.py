@@ -69,11 +69,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", choices=["plain", "mixed"], default="plain")
+    ap.add_argument("--precision", choices=["both", "plain", "mixed"], default="both",
+                    help="both: the plain FP64 line with the mixed leg beside it (default)")
     ap.add_argument("--points", type=int, default=None)
     ap.add_argument("--config", default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=20000)
+    ap.add_argument("--cpu-sample", type=int, default=4000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device copy first (scale reference for HBM counters)")
     ap.add_argument("--workload", choices=["eval", "batched", "surrogate", "grad"], default="eval",
@@ -124,10 +125,104 @@ def main():
         (build_s, info["n_components"], info["n_rows"], info["n_passes"], info["device_bytes"] / 1e9))
     X = torch.from_numpy(ws.points_for(cfg, n=n)).to(dev)
     m, d = cfg["m"], cfg["d"]
-    Y = torch.empty((n, m), dtype=torch.float64, device=dev)
-    prec = hd.PLAIN_FP64 if args.precision == "plain" else hd.MIXED
     hits, probes = hd.hdmr_eval_stats(model, X)
     log("nonzero basis products per point %.1f, lookups per point %.1f" % (hits / n, probes / n))
+    ceil = measured_ceilings()
+    legs = {}
+    outputs = {}
+    precisions = [args.precision] if args.precision != "both" else ["plain", "mixed"]
+    for name in precisions:
+        prec = hd.PLAIN_FP64 if name == "plain" else hd.MIXED
+        Y = torch.empty((n, m), dtype=torch.float64, device=dev)
+        legs[name] = run_leg(hd, model, X, Y, prec, name, args, info, hits, n, m, d, ceil)
+        outputs[name] = Y
+    head = precisions[0]
+    L = legs[head]
+    out = {
+        "metric": "HDMR-ASG point x output evaluations/sec at d=100, m=51",
+        "value": L["value"],
+        "unit": "point*outputs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": L["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if head == "plain" else "f32 basis, bf16x3 mfma, f64 sum",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: d=%d, %d components (%d one-dim + %d two-dim), adaptive sparse grids max level %d "
+                        "eps_gamma=%g, m=%d, %d next-state points, %s precision" %
+                        (args.config, d, info["n_components"], d, info["n_components"] - d, cfg["max_level"],
+                         cfg["eps_gamma"], m, n, head),
+            "grid_rows": info["n_rows"],
+            "build_s_untimed": build_s,
+            "nonzeros_per_point": hits / n,
+            "lookups_per_point": probes / n,
+            "parallelism": "single GPU (points)",
+        },
+        "roofline": L["roofline"],
+        "wall_s_timed_region": L["wall_s"],
+    }
+    if "mixed" in legs and head != "mixed":
+        M_ = legs["mixed"]
+        out["mixed"] = {"value": M_["value"], "ms_per_step": M_["ms_per_step"],
+                        "speedup_over_plain": L["ms_per_step"] / M_["ms_per_step"],
+                        "dtype": "f32 basis, bf16x3 mfma (6 products), f32 partial sums folded into f64 every 16 "
+                                 "passes, f64 c0",
+                        "roofline": M_["roofline"], "wall_s_timed_region": M_["wall_s"]}
+    if not args.no_cpu_baseline:
+        cb, sample_idx, ref = cpu_baseline(cfg, args.cpu_sample, ws)
+        cb["gpu_over_cpu"] = out["value"] / cb["value"]
+        out["cpu_baseline"] = cb
+        # error against the oracle on the baseline's sample (its outputs are the reference)
+        errs = {}
+        for name, Y in outputs.items():
+            Ys = Y[torch.from_numpy(sample_idx).to(dev)].cpu().numpy()
+            errs[name] = error_report(Ys, ref)
+        out["error_vs_oracle"] = {"sample": cb["sample"], **errs}
+        out["error_vs_oracle"]["bars"] = {"plain": "max-abs <= 1e-12",
+                                          "mixed": "per output max|err|/max|F| <= 1e-6"}
+    print(json.dumps(out), flush=True)
+
+
+def error_report(Y, ref):
+    """Max-abs error, worst per-output relative error max_p|err_o| / max_p|F_o|,
+    and normwise error of Y against the oracle's values ref."""
+    import numpy as np
+    err = np.abs(Y - ref)
+    per_out = err.max(axis=0) / np.maximum(np.abs(ref).max(axis=0), 1e-300)
+    return {"max_abs": float(err.max()), "worst_output_rel": float(per_out.max()),
+            "normwise": float(np.linalg.norm(Y - ref) / np.linalg.norm(ref))}
+
+
+def measured_ceilings():
+    """Run the device-ceiling microbenchmarks (paper_2202_06555_amd/bench_ceilings):
+    HBM copy, random accumulator-row read-modify-write, FP64/BF16 MFMA, FP64
+    VALU, LDS gather.  Returns the parsed lines, or {} if the program is absent."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_2202_06555_amd", "bench_ceilings")
+    if not os.path.exists(exe):
+        return {}
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    res = {"rmw": []}
+    for line in r.stdout.splitlines():
+        try:
+            o = json.loads(line)
+        except ValueError:
+            continue
+        if o.get("probe") == "rmw":
+            res["rmw"].append(o)
+        else:
+            res[o["probe"]] = o
+    return res
+
+
+def run_leg(hd, model, X, Y, prec, name, args, info, hits, n, m, d, ceil):
+    """Warm-up, then args.steps timed evaluations; device-event stage timing
+    and the roofline of the contraction kernel."""
+    import torch
     for _ in range(args.warmup):
         hd.hdmr_eval(model, X, Y, precision=prec)
     torch.cuda.synchronize()
@@ -145,24 +240,25 @@ def main():
     stages = {s: hd.hdmr_timing_read(s) for s in ("sort", "rows", "contract")}
     hd.hdmr_timing_enable(False)
     ms = ev0.elapsed_time(ev1) / args.steps
-    t = ms / 1e3
-    value = n * m / t
-    log("step %.2f ms; per step: sort %.1f ms, rows %.1f ms, contract %.1f ms" %
-        (ms, stages["sort"][0] / args.steps, stages["rows"][0] / args.steps, stages["contract"][0] / args.steps))
-
+    value = n * m / (ms / 1e3)
+    log("%s: step %.2f ms; per step: sort+rows (second stream, overlapped) %.1f ms, contract %.1f ms" %
+        (name, ms, (stages["sort"][0] + stages["rows"][0]) / args.steps, stages["contract"][0] / args.steps))
     # roofline of the contraction kernel (one launch per pass and 64-output chunk)
     c_ms, c_launches = stages["contract"]
     launches_per_step = c_launches / args.steps
     per_launch_s = c_ms / 1e3 / c_launches
     P = info["n_passes"]
+    AS = (m + 15) // 16 * 16
     flops_launch = 2.0 * hits * m / launches_per_step
-    mfma_peak = FP64_PEAK if prec == hd.PLAIN_FP64 else BF16_PEAK
+    plain = prec == hd.PLAIN_FP64
+    mfma_peak = FP64_PEAK if plain else BF16_PEAK
     # problem-level bytes of an evaluation: outputs once, points once, the model once
     alg_bytes_step = n * m * 8.0 + n * d * 8.0 + info["device_bytes"]
-    # bytes this design must move: every pass re-reads and re-writes the output rows
-    design_bytes_step = (n * m * 16.0 * P + info["n_rows"] * m * (8 if prec == hd.PLAIN_FP64 else 4) +
-                         n * (8.0 * info["pass_key_dims"] + 4.0 * P))
-    kern = KERNEL[args.precision]
+    # bytes this design must move per pass: the accumulator rows (AS values,
+    # FP64 plain / FP32 mixed) read and written, the points' key coordinates
+    acc_bytes = 8.0 if plain else 4.0
+    design_bytes_step = (n * AS * 2 * acc_bytes * P + n * (8.0 * info["pass_key_dims"] + 4.0 * P))
+    kern = KERNEL[name]
     traffic = _measured_traffic(kern, args.config)
     roof = {
         "bound": "mfma",
@@ -180,42 +276,49 @@ def main():
         "hbm_GBps_of_traffic": (traffic / per_launch_s / 1e9) if traffic else None,
         "hbm_frac_of_traffic": (traffic / per_launch_s / HBM_PEAK) if traffic else None,
         "stage_ms_per_step": {s: v[0] / args.steps for s, v in stages.items()},
+        "stage_note": "sort and rows run on a second stream, overlapped with the contraction",
     }
-    if prec == hd.MIXED:
+    if not plain:
         # six BF16 products per useful FMA, and the FP32 vector peak for reference
         roof["mfma_issued_frac"] = 6.0 * roof["frac"]
         roof["frac_of_fp32_vector_peak"] = flops_launch / per_launch_s / FP32_PEAK
-    out = {
-        "metric": "HDMR-ASG point x output evaluations/sec at d=100, m=51",
-        "value": value,
-        "unit": "point*outputs/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if prec == hd.PLAIN_FP64 else "f32 basis, bf16x3 mfma, f64 sum",
-        "data": "synthetic",
-        "config": {
-            "workload": "%s: d=%d, %d components (%d one-dim + %d two-dim), adaptive sparse grids max level %d "
-                        "eps_gamma=%g, m=%d, %d next-state points, %s precision" %
-                        (args.config, d, info["n_components"], d, info["n_components"] - d, cfg["max_level"],
-                         cfg["eps_gamma"], m, n, args.precision),
-            "grid_rows": info["n_rows"],
-            "build_s_untimed": build_s,
-            "nonzeros_per_point": hits / n,
-            "lookups_per_point": probes / n,
-            "parallelism": "single GPU (points)",
-        },
-        "roofline": roof,
-        "wall_s_timed_region": wall,
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample, ws)
-        out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
-    print(json.dumps(out), flush=True)
+    if ceil:
+        roof["measured_ceilings"] = ceiling_roofline(ceil, plain, flops_launch, per_launch_s, n, m, AS, P,
+                                                     launches_per_step)
+    return {"value": value, "ms_per_step": ms, "roofline": roof, "wall_s": wall}
+
+
+def ceiling_roofline(ceil, plain, flops_launch, per_launch_s, n, m, AS, P, launches_per_step):
+    """Multi-ceiling roofline of one contraction launch from the measured
+    ceilings: matrix-core time of the products as issued (output columns padded
+    to 16-wide tiles; six BF16 products per FMA in the mixed path) and the
+    accumulator read-modify-write time at the measured random-row rate (the
+    largest buffer of the ceiling run, 16-column line-aligned layout).  The
+    bound is the larger; frac = bound / measured launch time."""
+    pad = AS / m
+    if plain:
+        p_mfma = ceil["mfma_f64"]["TFLOPs"] * 1e12
+        issued = flops_launch * pad
+        acc_b = 8.0
+    else:
+        p_mfma = ceil["mfma_bf16"]["TFLOPs"] * 1e12
+        issued = flops_launch * pad * 6.0
+        acc_b = 4.0
+    rows = [r for r in ceil["rmw"] if r["layout"] == "colblock16_m64"]
+    big = max(rows, key=lambda r: r["rows"])
+    rmw_Bps = big["useful_GBps"] * 1e9
+    npass_launch = P / launches_per_step
+    rmw_bytes = n * AS * 2 * acc_b * npass_launch
+    if not plain:
+        rmw_bytes += n * AS * (4 + 16 + 4) * npass_launch / 16.0   # folds every 16 passes
+    t_mfma = issued / p_mfma
+    t_rmw = rmw_bytes / rmw_Bps
+    t_roof = max(t_mfma, t_rmw)
+    return {"mfma_ceiling_TFLOPs": p_mfma / 1e12, "rmw_ceiling_GBps": rmw_Bps / 1e9,
+            "hbm_copy_GBps": ceil.get("copy", {}).get("GBps"),
+            "t_mfma_ms": t_mfma * 1e3, "t_rmw_ms": t_rmw * 1e3, "t_roof_ms": t_roof * 1e3,
+            "t_measured_ms": per_launch_s * 1e3, "frac": t_roof / per_launch_s,
+            "binding": "mfma" if t_mfma >= t_rmw else "accumulator read-modify-write"}
 
 
 def _timed(fn, steps, warmup):
@@ -396,7 +499,13 @@ def bench_surrogate(args):
 
 def cpu_baseline(cfg, sample, ws):
     """The FP64 oracle (C, OpenMP over points, level-wise mode) on its own build
-    of the same workload, timed on this host's cores on a bounded sample."""
+    of the same workload, timed on this host's cores on a bounded sample:
+    median of 5 timed runs after one warm-up on all threads, and one run on a
+    single thread over the first eighth of the sample.  Returns the baseline
+    record, the sample's point indices and the oracle's values there."""
+    import platform
+    import statistics
+    import numpy as np
     import oracle
     tf = ws.test_function_for(cfg)
     t0 = time.time()
@@ -404,15 +513,37 @@ def cpu_baseline(cfg, sample, ws):
                                   max_level=cfg["max_level"], eps_gamma=cfg["eps_gamma"])
     log("oracle build %.1f s" % (time.time() - t0))
     X = ws.points_for(cfg, n=sample)
-    oracle.evaluate(model, X[:64])
+    threads = oracle.num_threads()
+    ref = oracle.evaluate(model, X)          # warm-up; also the reference values
+    times = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        oracle.evaluate(model, X)
+        times.append(time.perf_counter() - t0)
+    t = statistics.median(times)
+    n1 = max(1, sample // 8)
+    oracle.set_num_threads(1)
     t0 = time.perf_counter()
-    oracle.evaluate(model, X)
-    t = time.perf_counter() - t0
-    log("oracle eval of %d points: %.2f s" % (sample, t))
-    return {"value": sample * cfg["m"] / t, "unit": "point*outputs/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "first %d of the %d next-state points (seed %d), level-wise FP64 oracle with compensated sums"
-                      % (sample, cfg["n"], cfg["seed"])}
+    oracle.evaluate(model, X[:n1])
+    t1 = time.perf_counter() - t0
+    oracle.set_num_threads(threads)
+    log("oracle eval of %d points: median %.2f s on %d threads; %d points on 1 thread %.2f s" %
+        (sample, t, threads, n1, t1))
+    cpu = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    rec = {"value": sample * cfg["m"] / t, "unit": "point*outputs/s", "cores": threads, "kind": "oracle",
+           "sample": "first %d of the %d next-state points (seed %d), level-wise FP64 oracle with compensated "
+                     "sums; median of 5 runs after 1 warm-up" % (sample, cfg["n"], cfg["seed"]),
+           "single_thread_value": n1 * cfg["m"] / t1, "single_thread_sample": n1,
+           "nproc": os.cpu_count(), "cpu_model": cpu}
+    return rec, np.arange(sample), ref
 
 
 if __name__ == "__main__":

@@ -104,12 +104,19 @@ def lib():
             L.orc_grid_free.argtypes = [vp]
             L.orc_num_threads.restype = ctypes.c_int
             L.orc_num_threads.argtypes = []
+            L.orc_set_num_threads.restype = None
+            L.orc_set_num_threads.argtypes = [ctypes.c_int]
             _LIB = L
     return _LIB
 
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (timing only)."""
+    lib().orc_set_num_threads(int(n))
 
 
 # ---------------------------------------------------------------------------

@@ -823,3 +823,13 @@ int orc_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Thread count of the parallel loops that follow (harness control for the
+ * single-thread timing; no effect on results). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
