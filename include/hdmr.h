@@ -119,6 +119,23 @@ int hdmr_model_from_surpluses(int32_t d, int32_t m, const double *c0, int32_t n_
 int hdmr_eval(const hdmr_model *model, const double *points, int64_t n, double *values, int32_t m,
               int32_t precision, hdmr_stream_t stream);
 
+/* hdmr_eval without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and precisions as hdmr_eval, and the
+ * same kernels.  The cell-sorted path (HDMR_MIXED, or n >= 16384 points in
+ * plain precision) takes its workspace from a static device array of 256 MiB
+ * that the library holds on every device it runs on until the process ends;
+ * it also uses a second stream and events created once per device at set-up
+ * (hdmr_init, else the first call on that device).  A call whose workspace
+ * would exceed 256 MiB (about n (8 d + 8 AS + 4 AS [mixed] + 90) bytes plus
+ * the model's cell lists, AS = m rounded up to 16) is rejected with
+ * HDMR_EINVAL before any work is enqueued.  Every call on one device shares
+ * that device's array and set-up: calls that overlap on one device (other
+ * streams or threads) race and must be serialised by the caller; the array
+ * keeps the last call's contents, and every call initialises what it reads. */
+int hdmr_eval_noalloc(const hdmr_model *model, const double *points, int64_t n, double *values, int32_t m,
+                      int32_t precision, hdmr_stream_t stream);
+
 /* F and its gradient: grad (dev, n x d x m) receives dF_o/dx_q as the right
  * partial derivative (the left one at x_q = 1; zero outside [0,1] and for
  * dimensions no component uses).  values may be NULL. */

@@ -368,6 +368,21 @@ int check_eval_args(const hdmr_model *model, const double *points, int64_t n, co
   return HDMR_OK;
 }
 
+// hdmr_eval after argument checks: the gather kernel (no workspace) or the
+// cell-sorted path with its workspace allocated (ws == NULL) or supplied.
+int eval_any(const hdmr_model *model, const double *points, int64_t n, double *values, int precision,
+             hipStream_t stream, void *ws, size_t ws_bytes, hipEvent_t *events) {
+  if (precision == HDMR_MIXED || use_sorted_path(model, n))
+    return eval_sorted(model, points, n, values, precision, stream, 0, nullptr, ws, ws_bytes, events);
+  const ModelView M = model->view();
+  const size_t per = ((size_t)M.d * 8 + 64 * 8 + 64 * 4 + 15) & ~(size_t)15;
+  const size_t smem = per * WAVES_PER_BLOCK;
+  if (smem > 65536) return fail(HDMR_EUNSUPPORTED, "d too large for the LDS staging of points");
+  EVAL_DISPATCH(k_eval_fp64, smem, M, points, n, values);
+  HDMR_HIP(hipGetLastError());
+  return HDMR_OK;
+}
+
 }  // namespace
 
 }  // namespace hdmr
@@ -384,16 +399,30 @@ int hdmr_eval(const hdmr_model *model, const double *points, int64_t n, double *
   if (precision != HDMR_PLAIN_FP64 && precision != HDMR_MIXED) return fail(HDMR_EINVAL, "unknown precision");
   if (n == 0) return HDMR_OK;
   if ((rc = set_device_of(model))) return rc;
-  hipStream_t stream = (hipStream_t)stream_;
-  if (precision == HDMR_MIXED) return eval_sorted(model, points, n, values, HDMR_MIXED, stream);
-  if (use_sorted_path(model, n)) return eval_sorted(model, points, n, values, HDMR_PLAIN_FP64, stream);
-  const ModelView M = model->view();
-  const size_t per = ((size_t)M.d * 8 + 64 * 8 + 64 * 4 + 15) & ~(size_t)15;
-  const size_t smem = per * WAVES_PER_BLOCK;
-  if (smem > 65536) return fail(HDMR_EUNSUPPORTED, "d too large for the LDS staging of points");
-  EVAL_DISPATCH(k_eval_fp64, smem, M, points, n, values);
-  HDMR_HIP(hipGetLastError());
-  return HDMR_OK;
+  return eval_any(model, points, n, values, precision, (hipStream_t)stream_, nullptr, 0, nullptr);
+}
+
+int hdmr_eval_noalloc(const hdmr_model *model, const double *points, int64_t n, double *values, int32_t m,
+                      int32_t precision, hdmr_stream_t stream_) {
+  clear_error();
+  int rc = check_eval_args(model, points, n, values, m, true);
+  if (rc) return rc;
+  if (precision != HDMR_PLAIN_FP64 && precision != HDMR_MIXED) return fail(HDMR_EINVAL, "unknown precision");
+  if (n == 0) return HDMR_OK;
+  if ((rc = set_device_of(model))) return rc;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  hipEvent_t *events = nullptr;
+  if ((rc = noalloc_workspace(model->device, &ws, &ws_bytes, &events))) return rc;
+  if (precision == HDMR_MIXED || use_sorted_path(model, n)) {
+    size_t need = 0;
+    if ((rc = eval_sorted_workspace(model, n, precision, &need))) return rc;
+    if (need > ws_bytes)
+      return fail(HDMR_EINVAL, "hdmr_eval_noalloc: " + std::to_string(n) + " points of this model need " +
+                                   std::to_string(need) + " bytes of workspace; the static workspace holds " +
+                                   std::to_string(ws_bytes) + " (use hdmr_eval, or fewer points per call)");
+  }
+  return eval_any(model, points, n, values, precision, (hipStream_t)stream_, ws, ws_bytes, events);
 }
 
 int hdmr_eval_stats(const hdmr_model *model, const double *points, int64_t n, int64_t *hits, int64_t *probes,

@@ -1042,8 +1042,52 @@ int eval_sorted_workspace(const hdmr_model *model, int64_t n, int precision, siz
   return HDMR_OK;
 }
 
+// Workspace of hdmr_eval_noalloc: a file-scope device array, one copy per
+// device, held until the process ends.  Host code reaches it only through the
+// address hipGetSymbolAddress returns on that device (the array's name in host
+// code is a host-side stand-in, not a device address).  The noalloc path also
+// keeps its second stream and its events per device, created at set-up.
+constexpr size_t NOALLOC_BYTES = (size_t)256 << 20;
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+
+namespace {
+struct NoallocDev {
+  void *ptr = nullptr;
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+};
+std::mutex g_noalloc_mu;
+std::vector<NoallocDev> g_noalloc;
+}  // namespace
+
+int noalloc_setup(int device) {
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if ((int)g_noalloc.size() <= device) g_noalloc.resize((size_t)device + 1);
+  NoallocDev &D = g_noalloc[(size_t)device];
+  if (D.ptr) return HDMR_OK;
+  int cur = -1;
+  HDMR_HIP(hipGetDevice(&cur));
+  if (cur != device) return fail(HDMR_EDEVICE, "noalloc set-up: device " + std::to_string(device) + " is not current");
+  void *p = nullptr;
+  HDMR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) return fail(HDMR_EDEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+  if (!side_stream(device)) return fail(HDMR_EDEVICE, "second stream could not be created");
+  for (hipEvent_t &e : D.ev) HDMR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  D.ptr = p;
+  return HDMR_OK;
+}
+
+int noalloc_workspace(int device, void **ptr, size_t *bytes, hipEvent_t **events) {
+  int rc = noalloc_setup(device);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  *ptr = g_noalloc[(size_t)device].ptr;
+  *bytes = NOALLOC_BYTES;
+  *events = g_noalloc[(size_t)device].ev;
+  return HDMR_OK;
+}
+
 int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, int precision, hipStream_t stream,
-                int variant, double *G, void *ws_base, size_t ws_bytes) {
+                int variant, double *G, void *ws_base, size_t ws_bytes, hipEvent_t *events) {
   const ModelView M = model->view();
   const int d = M.d, m = M.m;
   const int AS = (m + 15) & ~15;  // accumulator row stride: whole 16-output slices
@@ -1086,8 +1130,13 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
   hipEvent_t ev_ready = nullptr, ev_side_end = nullptr, ev_sorted[2] = {nullptr, nullptr},
              ev_done[2] = {nullptr, nullptr};
   hipError_t e = side ? hipSuccess : hipErrorInvalidValue;
-  for (hipEvent_t *ev : {&ev_ready, &ev_side_end, &ev_sorted[0], &ev_sorted[1], &ev_done[0], &ev_done[1]})
-    if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+  hipEvent_t *evs[6] = {&ev_ready, &ev_side_end, &ev_sorted[0], &ev_sorted[1], &ev_done[0], &ev_done[1]};
+  for (int i = 0; i < 6; ++i) {
+    if (events)
+      *evs[i] = events[i];  // the caller's persistent events
+    else if (e == hipSuccess)
+      e = hipEventCreateWithFlags(evs[i], hipEventDisableTiming);
+  }
   const unsigned gs = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
   // contraction workgroups: about one per work item (items hold <= CHUNK
   // points of one cell), within [1024, TILE_GRID]; each walks the items
@@ -1197,8 +1246,9 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
     if (G) hipLaunchKernelGGL(k_nan_fix, dim3(gs), dim3(256), 0, stream, G, W.nanflag, n, d * m);
     e = hipGetLastError();
   }
-  for (hipEvent_t ev : {ev_ready, ev_side_end, ev_sorted[0], ev_sorted[1], ev_done[0], ev_done[1]})
-    if (ev) (void)hipEventDestroy(ev);
+  if (!events)
+    for (hipEvent_t ev : {ev_ready, ev_side_end, ev_sorted[0], ev_sorted[1], ev_done[0], ev_done[1]})
+      if (ev) (void)hipEventDestroy(ev);
   if (own) (void)hipFreeAsync(base, stream);
   if (e != hipSuccess) return hip_fail(e, "sorted evaluation");
   return HDMR_OK;

@@ -148,10 +148,18 @@ void keep_pool_memory(int device);
 // gradient is computed as well.
 // ws_base (device, ws_bytes bytes) supplies the workspace; with NULL it is
 // allocated stream-ordered on the device's pool and released at the end.
+// events (6, optional): persistent events to use instead of per-call ones.
 int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, int precision, hipStream_t stream,
-                int variant = 0, double *G = nullptr, void *ws_base = nullptr, size_t ws_bytes = 0);
+                int variant = 0, double *G = nullptr, void *ws_base = nullptr, size_t ws_bytes = 0,
+                hipEvent_t *events = nullptr);
 // Workspace bytes eval_sorted needs for n points at that precision.
 int eval_sorted_workspace(const hdmr_model *model, int64_t n, int precision, size_t *bytes);
+
+// The static workspace of hdmr_eval_noalloc on a device (eval_sorted.hip):
+// set-up once per device with that device current (address of the device
+// array, the second stream, persistent events), then its address and size.
+int noalloc_setup(int device);
+int noalloc_workspace(int device, void **ptr, size_t *bytes, hipEvent_t **events);
 
 // Drop every cached batched-launch graph that refers to the model (batched.hip).
 void batched_forget(const hdmr_model *model);

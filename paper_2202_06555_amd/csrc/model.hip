@@ -444,7 +444,7 @@ int hdmr_init(int32_t device) {
   if (device < 0 || device >= n) return fail(HDMR_EDEVICE, "no such HIP device");
   HDMR_HIP(hipSetDevice(device));
   HDMR_HIP(hipFree(nullptr));
-  return HDMR_OK;
+  return noalloc_setup(device);
 }
 
 int hdmr_model_from_surpluses(int32_t d, int32_t m, const double *c0, int32_t n_components,

@@ -31,6 +31,7 @@ EXPORTS = (
     "hdmr_init", "asg_build_components", "hdmr_model_from_surpluses", "hdmr_eval", "hdmr_eval_grad",
     "hdmr_get_info", "hdmr_export_component", "hdmr_free", "hdmr_last_error", "hdmr_eval_stats",
     "hdmr_timing_enable", "hdmr_timing_read", "hdmr_model_save", "hdmr_model_load", "hdmr_eval_batched",
+    "hdmr_eval_noalloc",
     # include/hdmr_surrogate.h
     "mlp_param_count", "mlp_create", "mlp_get_params", "mlp_set_standardization", "mlp_fit_standardization",
     "mlp_get_standardization", "mlp_forward", "mlp_loss_grads", "mlp_train", "mlp_free", "hdmr_model_select",
@@ -80,6 +81,7 @@ def lib():
                 "asg_build_components": [vp, vp, vp, vp],
                 "hdmr_model_from_surpluses": [i32, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp],
                 "hdmr_eval": [vp, vp, i64, vp, i32, i32, vp],
+                "hdmr_eval_noalloc": [vp, vp, i64, vp, i32, i32, vp],
                 "hdmr_eval_grad": [vp, vp, i64, vp, vp, i32, vp],
                 "hdmr_get_info": [vp, vp],
                 "hdmr_eval_stats": [vp, vp, i64, vp, vp, vp],
@@ -240,6 +242,17 @@ def hdmr_eval(model: Model, points, values=None, precision=PLAIN_FP64, stream=No
         values = torch.empty((n, inf["m"]), dtype=torch.float64, device=points.device)
     _check(lib().hdmr_eval(model.handle, _dev(points, "points", (n, inf["d"])), n,
                            _dev(values, "values", (n, inf["m"])), inf["m"], int(precision), _stream_ptr(stream)))
+    return values
+
+
+def hdmr_eval_noalloc(model: Model, points, values, precision=PLAIN_FP64, stream=None):
+    """hdmr_eval into the caller's ``values`` (n, m) without device allocation
+    (static library workspace); returns ``values``."""
+    inf = hdmr_get_info(model)
+    n = points.shape[0]
+    _check(lib().hdmr_eval_noalloc(model.handle, _dev(points, "points", (n, inf["d"])), n,
+                                   _dev(values, "values", (n, inf["m"])), inf["m"], int(precision),
+                                   _stream_ptr(stream)))
     return values
 
 
