@@ -64,7 +64,7 @@ typedef int (*hdmr_fn)(const double *X, int64_t n, int32_t d, double *Y, int32_t
 int hdmr_init(int32_t device);
 
 /* ---------------------------------------------------------------------------
- * Building a model from a function (Alg. 2 without the eta/rho criteria).
+ * Building a model from a function (Alg. 2).
  *
  * For every index set S (explicit list, or all 1 <= |S| <= max_order), an
  * adaptive sparse grid is grown by ascending level sums from the root
@@ -83,6 +83,20 @@ int hdmr_init(int32_t device);
  * eq (4.2) coefficients b_S and c0 = b_empty f(xbar).
  * f is called on the host, once per level sum with every new node of every
  * component (rows are deduplicated).  The result lives on the current device.
+ *
+ * With eps_eta > 0 or eps_rho > 0 the build follows Alg. 2: the expansion
+ * orders k = 1, 2, ... are built in turn; the candidates of order k are the
+ * index sets of size k (of the explicit list, or all of them up to
+ * max_order) that contain no rejected set.  With Q f_u the quadrature
+ * (eq (3.7)) of the interpolant of the component function u_S (computed on
+ * the device) and Q f_empty = f(xbar), D_k = ||sum of Q f_v over the kept v
+ * with |v| < k||_2 (2-norm over the m outputs).  A candidate of order >= 2 is
+ * kept when eta_u = ||Q f_u||_2 / D_k > eps_eta (eq (3.19)), else it joins
+ * the reject set Z and no superset of it is built (eps_eta <= 0: all kept).
+ * After order k, rho_k = ||sum of Q f_u over the kept order-k u||_2 / D_k
+ * (eq (3.18)); order k+1 follows only if rho_k > eps_rho (eps_rho <= 0:
+ * always).  The model holds the kept components (form 1: b_S over the kept
+ * family); hdmr_build_report returns the candidates, eta, kept flags and rho.
  * ------------------------------------------------------------------------- */
 typedef struct {
   int32_t d, m;                 /* input dimension, number of outputs                     */
@@ -96,10 +110,25 @@ typedef struct {
   const int32_t *comp_offsets;  /* host, n_components+1 offsets into comp_dims            */
   const int32_t *comp_dims;     /* host, the index sets, each strictly increasing         */
   int32_t form;                 /* 0: component form; 1: eq (4.2) form                    */
-  double eps_eta, eps_rho;      /* eq (3.19)/(3.18) criteria: must be <= 0 here           */
+  double eps_eta, eps_rho;      /* eq (3.19)/(3.18) thresholds of Alg. 2 (<= 0: off)      */
 } asg_build_params;
 
 int asg_build_components(const asg_build_params *params, hdmr_fn f, void *user, hdmr_model **out);
+
+/* Report of an adaptive build (Alg. 2).  *n_candidates and *n_orders receive
+ * the counts; the arrays (host, may be NULL; query the counts first) receive
+ * per candidate in build order: cand_k = |S|, cand_dims (n_candidates x 4,
+ * -1 padded), eta (eq (3.19); NaN where not tested: order 1, or eps_eta <= 0),
+ * kept (1/0); rho (n_orders values, eq (3.18)).  Models not built with the
+ * criteria report zero candidates. */
+int hdmr_build_report(const hdmr_model *model, int32_t *n_candidates, int32_t *n_orders, int32_t *cand_k,
+                      int32_t *cand_dims, double *eta, uint8_t *kept, double *rho);
+
+/* Quadrature of eq (3.7) over [0,1]^d on the device: q (host, n_components x
+ * m, may be NULL) receives Q u_S = sum_j alpha_j 2^-|l_j|_1 per component (the
+ * integral of a zero-boundary hat of level l is 2^-l); total (host, m, may be
+ * NULL) receives c0 + sum_S w_S Q u_S, the integral of F.  Synchronous. */
+int hdmr_quadrature(const hdmr_model *model, double *q, double *total);
 
 /* Model from given grids and surpluses (host arrays, copied to the current
  * device).  Component s has index set comp_dims[comp_offsets[s] ..
@@ -113,6 +142,19 @@ int hdmr_model_from_surpluses(int32_t d, int32_t m, const double *c0, int32_t n_
                               const int64_t *comp_npts, const uint8_t *levels,
                               const uint32_t *indices, const double *surpluses,
                               const double *weights, hdmr_model **out);
+
+/* The naive evaluation of eq (3.16) (Sec. 4.1, Sec. 5.1): a new model whose
+ * evaluation sums, for every retained index set u (the components of src)
+ * and every nonempty v subset u, (-1)^(|u|-|v|) times the interpolant of the
+ * cut function g_v as its own term, recomputing the interpolants that several
+ * u share, plus c0 = f(xbar) sum_{u in U + {empty}} (-1)^|u|.  src must hold
+ * the cut-function surpluses g_v of a family closed under subsets (a form 1
+ * build); its weights and c0 are not used.  f_anchor (host, m values) is
+ * f(xbar).  Evaluated with hdmr_eval it gives the same values as src (the
+ * eq (4.2) regrouping a(x)^T b) up to rounding, with the work of eq (3.16)
+ * term by term.  A family that is not closed under subsets gives HDMR_EINVAL.
+ * The new model lives on the current device and is freed with hdmr_free. */
+int hdmr_model_naive(const hdmr_model *src, const double *f_anchor, hdmr_model **out);
 
 /* F at n points: points (dev, n x d), values (dev, n x m).  m must equal the
  * model's m.  precision is HDMR_PLAIN_FP64 or HDMR_MIXED.  n = 0 is a no-op. */

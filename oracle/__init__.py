@@ -20,6 +20,12 @@ Pinned functions and their pins (tests/test_oracle_*.py):
   grad                  central differences inside cells, hand cases
   build_model           regular limit == regular_grid, anchor-line zeros
   paper_coefficients    constant reproduction, closed form, Fig. 4 example
+  evaluate_naive        equals the eq (4.2) regrouping a(x)^T b; telescoping at
+                        HDMR nodes (eq (2.2.6))
+  quadrature            exact integral of the piecewise-(bi)linear interpolant
+                        by a midpoint rule finer than the finest level
+  build_ddsg            eta / rho / Z against closed forms for functions whose
+                        component functions lie in the hat span
   cut_hdmr_exact        Fig. 3 truncation exactness
 """
 from __future__ import annotations
@@ -336,6 +342,82 @@ def build_model(comps, d, m, anchor, fn, user=None, max_level=7, level_rule=0, e
     return model, {"accepted": acc, "alpha_cut": ag, "alpha_component": au, "f_anchor": f_anchor}
 
 
+def quadrature(model):
+    """eq (3.7) per component: Q u_S = sum_j alpha_j prod_q int phi_{l_jq,i_jq}
+    = sum_j alpha_j 2^(-|l_j|_1) (the integral of a zero-boundary hat of level
+    l over [0,1] is its support's half-width 2^-l).  Returns (ncomp, m)."""
+    out = np.zeros((len(model["comps"]), model["m"]))
+    for s, (lv, al) in enumerate(zip(model["levels"], model["alpha"])):
+        if lv.shape[0]:
+            w = np.ldexp(1.0, -lv.astype(np.int64).sum(axis=1))
+            out[s] = (w[:, None] * al).sum(axis=0)
+    return out
+
+
+def build_ddsg(d, m, anchor, fn, max_order, eps_eta, eps_rho, comps=None, max_level=7, level_rule=0,
+               eps_gamma=1e-4, refine_rule=0, form="component"):
+    """Alg. 2: the adaptive DDSG build with the active-dimension criterion
+    (eq (3.19)) and the expansion criterion (eq (3.18)).
+
+    Expansion orders k = 1, 2, ... max_order in turn.  The candidates of order
+    k are the index sets of size k (all of them, or those of ``comps``) that
+    contain no rejected set of Z.  Each candidate's grid is grown on its cut
+    function (build_model).  With Q f_u the quadrature (eq (3.7)) of the
+    component function's interpolant and Q f_empty = f(xbar), the order's
+    denominator is D_k = || sum over retained u with |u| <= k-1 of Q f_u ||_2
+    (2-norm over the m outputs).  A candidate of order k >= 2 is kept when
+    eta_u = ||Q f_u||_2 / D_k > eps_eta, else it joins Z (order-1 candidates
+    are always kept); with eps_eta <= 0 every candidate is kept.  After the
+    order, rho_k = || sum over the kept candidates of Q f_u ||_2 / D_k, and the
+    build proceeds to order k+1 only if rho_k > eps_rho (eps_rho <= 0: always,
+    up to max_order).  Returns (model, report) with the kept components in
+    build order, ``form`` as in build_model (the eq (4.2) coefficients over
+    the kept family), and the report's candidates, eta, Z and rho."""
+    f_anchor = _call(fn, np.asarray(anchor, dtype=np.float64)[None, :], d, m)[0]
+    allowed = None if comps is None else {tuple(sorted(S)) for S in comps}
+    Z, kept, rho, cands, eta = [], [], [], [], {}
+    Qf = {(): f_anchor}
+    parts = {"levels": [], "indices": [], "alpha_u": [], "alpha_g": []}
+    for k in range(1, max_order + 1):
+        C = [c for c in itertools.combinations(range(d), k)
+             if (allowed is None or c in allowed) and not any(set(z) <= set(c) for z in Z)]
+        if not C:
+            break
+        model_k, info_k = build_model(C, d, m, anchor, fn, max_level=max_level, level_rule=level_rule,
+                                      eps_gamma=eps_gamma, refine_rule=refine_rule, form="component")
+        Qk = quadrature(model_k)
+        denom = np.linalg.norm(sum(Qf[v] for v in kept + [()] if len(v) <= k - 1))
+        keep_k = []
+        for s, c in enumerate(C):
+            cands.append(c)
+            if k >= 2 and eps_eta > 0:
+                eta[c] = float(np.linalg.norm(Qk[s]) / denom)
+                if not eta[c] > eps_eta:
+                    Z.append(c)
+                    continue
+            keep_k.append(s)
+        for s in keep_k:
+            Qf[C[s]] = Qk[s]
+            kept.append(C[s])
+            parts["levels"].append(model_k["levels"][s])
+            parts["indices"].append(model_k["indices"][s])
+            parts["alpha_u"].append(info_k["alpha_component"][s])
+            parts["alpha_g"].append(info_k["alpha_cut"][s])
+        r = float(np.linalg.norm(sum((Qk[s] for s in keep_k), np.zeros(m))) / denom)
+        rho.append(r)
+        if eps_rho > 0 and not r > eps_rho:
+            break
+    if form == "component":
+        model = {"d": d, "m": m, "c0": f_anchor, "comps": kept, "weights": np.ones(len(kept)),
+                 "levels": parts["levels"], "indices": parts["indices"], "alpha": parts["alpha_u"]}
+    else:
+        b = paper_coefficients([()] + kept, d)
+        model = {"d": d, "m": m, "c0": b[()] * f_anchor, "comps": kept,
+                 "weights": np.asarray([float(b[S]) for S in kept]),
+                 "levels": parts["levels"], "indices": parts["indices"], "alpha": parts["alpha_g"]}
+    return model, {"candidates": cands, "eta": eta, "Z": Z, "rho": rho, "f_anchor": f_anchor}
+
+
 def _call(fn, X, d, m):
     if callable(fn):
         return np.asarray(fn(np.ascontiguousarray(X)), dtype=np.float64).reshape(X.shape[0], m)
@@ -367,6 +449,39 @@ def paper_coefficients(index_sets, d=None):
                 b += (-1) ** (len(fu) - len(fs))
         out[S] = b
     return out
+
+
+def evaluate_naive(model, X, f_anchor):
+    r"""eq (3.16) term by term: sum over the retained index sets u (the
+    model's components, plus the empty set) and every v subset u of
+    (-1)^(|u|-|v|) times the sparse-grid interpolant of the cut function
+    g_v = f(xbar \ x_v), with g_empty = f(xbar) = ``f_anchor`` (m values).
+    The model must hold the surpluses of the cut functions g_v (the eq (4.2)
+    form of a build) for a family closed under subsets; its weights and c0 are
+    not used.  Each g_v is re-evaluated for every u that contains it, as the
+    direct implementation of eq (3.16) does."""
+    X = np.asarray(X, dtype=np.float64)
+    comps = [tuple(S) for S in model["comps"]]
+    where = {S: s for s, S in enumerate(comps)}
+    f_anchor = np.asarray(f_anchor, dtype=np.float64)
+
+    def g(v):
+        if not v:
+            return np.broadcast_to(f_anchor, (X.shape[0], model["m"]))
+        s = where[v]
+        sub = {"d": model["d"], "m": model["m"], "c0": np.zeros(model["m"]), "comps": [v],
+               "weights": np.ones(1), "levels": [model["levels"][s]], "indices": [model["indices"][s]],
+               "alpha": [model["alpha"][s]]}
+        return evaluate(sub, X)
+
+    total = np.zeros((X.shape[0], model["m"]))
+    for u in [()] + comps:
+        for r in range(len(u) + 1):
+            for v in itertools.combinations(u, r):
+                if v not in where and v:
+                    raise ValueError("index set %r of %r is not retained" % (v, u))
+                total = total + ((-1) ** (len(u) - r)) * g(v)
+    return total
 
 
 def cut_hdmr_exact(f, xbar, order, X):

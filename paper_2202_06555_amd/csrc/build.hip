@@ -1,5 +1,5 @@
-// asg_build_components: adaptive cut-HDMR build (Alg. 2 without the eta/rho
-// criteria) with FP64 hierarchisation on the device.
+// asg_build_components: adaptive cut-HDMR build (Alg. 2) with FP64
+// hierarchisation and quadrature on the device.
 //
 // All components advance together by level sum s.  Per step:
 //   host   : the new nodes of every component (root first, then admitted
@@ -14,11 +14,18 @@
 //   host   : the new level multi-indices join the lookup directory and the
 //            children (l + e_q, 2 i_q -+ 1) of accepted nodes are admitted by
 //            the parent rule (Sec. 3.1 exclusion).
+// With the Alg. 2 criteria (eps_eta or eps_rho > 0) the expansion orders are
+// built in turn: the candidates of order k (index sets of size k that contain
+// no rejected set of Z) are grown as above, k_quadrature_rows forms the
+// quadrature (eq (3.7)) of every candidate's component interpolant on the
+// device, and the host applies the active-dimension test (eq (3.19)) and the
+// expansion test (eq (3.18)) to those m-vectors.
 // At the end the surpluses of u_S (form 0) or of g_S with the eq (4.2)
-// weights (form 1) are gathered into a regular model.
+// weights (form 1) of the kept components are gathered into a regular model.
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <limits>
 #include <cstring>
 #include <unordered_map>
 
@@ -123,6 +130,30 @@ __global__ __launch_bounds__(256) void k_hierarchize_fp64(const TupDesc *__restr
   }
 }
 
+// Quadrature of eq (3.7) for a set of components: q[c * m + o] = sum over the
+// listed rows r of component c (row[off[c] .. off[c+1])) of wt[r] *
+// A[row[r] * lda + col + o], wt = 2^-|l|_1 the integral of the row's tensor
+// basis function.  One workgroup per component; the four waves take every
+// fourth row and their partial sums are added in a fixed order.
+__global__ __launch_bounds__(256) void k_quadrature_rows(const double *__restrict__ A, int lda, int col, int m,
+                                                         const int64_t *__restrict__ row,
+                                                         const double *__restrict__ wt,
+                                                         const int64_t *__restrict__ off, double *__restrict__ q) {
+  __shared__ double part[WAVES_PER_BLOCK][WAVE];
+  const int c = blockIdx.x, lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  for (int o0 = 0; o0 < m; o0 += WAVE) {
+    const int o = o0 + lane;
+    double sum = 0.0;
+    if (o < m)
+      for (int64_t r = off[c] + w; r < off[c + 1]; r += WAVES_PER_BLOCK)
+        sum = fma(wt[r], A[row[r] * lda + col + o], sum);
+    part[w][lane] = sum;
+    __syncthreads();
+    if (w == 0 && o < m) q[(int64_t)c * m + o] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+    __syncthreads();
+  }
+}
+
 struct NodeKey {
   std::array<uint8_t, KMAX> l;
   std::array<uint32_t, KMAX> i;
@@ -224,10 +255,10 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
   if (P->level_rule != 0 && P->level_rule != 1) return fail(HDMR_EINVAL, "level_rule must be 0 or 1");
   if (P->refine_rule != 0 && P->refine_rule != 1) return fail(HDMR_EINVAL, "refine_rule must be 0 or 1");
   if (P->form != 0 && P->form != 1) return fail(HDMR_EINVAL, "form must be 0 or 1");
-  if (P->eps_eta > 0.0 || P->eps_rho > 0.0)
-    return fail(HDMR_EUNSUPPORTED, "the eta/rho expansion criteria are not implemented (pass values <= 0)");
-  // ---- component list ----
-  std::vector<CompState> C;
+  const bool criteria = P->eps_eta > 0.0 || P->eps_rho > 0.0;
+  if (!(P->eps_eta == P->eps_eta) || !(P->eps_rho == P->eps_rho)) return fail(HDMR_EINVAL, "eps_eta / eps_rho NaN");
+  // ---- index sets requested (all of them, or the candidates of Alg. 2) ----
+  std::vector<CompState> all;
   if (P->n_components > 0) {
     if (!P->comp_offsets || !P->comp_dims) return fail(HDMR_EINVAL, "null component list");
     for (int s = 0; s < P->n_components; ++s) {
@@ -239,7 +270,7 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
         if (c.dims[q] < 0 || c.dims[q] >= d || (q && c.dims[q] <= c.dims[q - 1]))
           return fail(HDMR_EINVAL, "component dimensions must be strictly increasing and < d");
       }
-      C.push_back(std::move(c));
+      all.push_back(std::move(c));
     }
   } else {
     if (P->max_order < 1 || P->max_order > KMAX) return fail(HDMR_EUNSUPPORTED, "max_order must be in [1,4]");
@@ -251,7 +282,7 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
         CompState c;
         c.k = k;
         for (int q = 0; q < k; ++q) c.dims[q] = v[q];
-        C.push_back(std::move(c));
+        all.push_back(std::move(c));
         int q = k - 1;
         while (q >= 0 && v[q] == d - k + q) --q;
         if (q < 0) break;
@@ -260,16 +291,16 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
       }
     }
   }
-  const int ncomp = (int)C.size();
   std::vector<double> anchor(P->anchor, P->anchor + d);
-  for (auto &c : C) {
+  auto add_root = [](CompState &c) {
     NodeKey root{};
     for (int q = 0; q < c.k; ++q) {
       root.l[q] = 1;
       root.i[q] = 1;
     }
     c.pending.push_back(root);
-  }
+  };
+  std::vector<CompState> C;  // components grown so far, in build order
   // ---- row cache for f(xbar \ x_v) with |v| < |S| ----
   std::unordered_map<RowKey, int64_t, RowKeyHash> cache;
   std::vector<double> cache_val;
@@ -277,6 +308,9 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
   std::vector<TupDesc> h_tups;
   int64_t tab_used = 0, rows_used = 0;
   int32_t lsum_top = P->level_rule == 1 ? P->max_level + KMAX - 1 : P->max_level * KMAX;
+  // grows every component of C that has pending nodes (new roots) to the end
+  auto run_steps = [&]() -> int {
+  const int ncomp = (int)C.size();
   for (int32_t step = 1; step <= lsum_top; ++step) {
     // ---- collect this step's nodes ----
     struct NewNode {
@@ -554,52 +588,234 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
       c.pending.erase(std::unique(c.pending.begin(), c.pending.end()), c.pending.end());
     }
   }
-  // ---- assemble the model ----
+  return HDMR_OK;
+  };  // run_steps
   std::vector<double> f_anchor((size_t)m);
-  {
-    RowKey rk{};
-    auto it = cache.find(rk);
-    if (it != cache.end()) {
-      std::memcpy(f_anchor.data(), &cache_val[(size_t)it->second * m], sizeof(double) * m);
-    } else if (f(anchor.data(), 1, d, f_anchor.data(), m, user) != 0) {
-      return fail(HDMR_ECALLBACK, "the user function returned an error");
+  if (f(anchor.data(), 1, d, f_anchor.data(), m, user) != 0)
+    return fail(HDMR_ECALLBACK, "the user function returned an error");
+  auto contains = [](const CompState &u, const int32_t *dims, int k) {
+    for (int q = 0; q < k; ++q) {
+      bool found = false;
+      for (int r = 0; r < u.k; ++r) found |= (u.dims[r] == dims[q]);
+      if (!found) return false;
+    }
+    return true;
+  };
+  std::vector<int> keep;  // kept components (indices into C), in build order
+  std::vector<DdsgCandidate> report;
+  std::vector<double> report_rho;
+  if (!criteria) {
+    C = std::move(all);
+    for (auto &c : C) add_root(c);
+    int rc = run_steps();
+    if (rc) return rc;
+    for (int s = 0; s < (int)C.size(); ++s) keep.push_back(s);
+  } else {
+    // Alg. 2: expansion orders in turn; eq (3.19) rejects candidates into Z,
+    // eq (3.18) ends the expansion
+    int kmax = 0;
+    for (const auto &c : all) kmax = std::max(kmax, c.k);
+    std::vector<std::vector<int32_t>> Z;
+    std::vector<double> below(f_anchor);  // sum of Q f_v over kept v, |v| < k, and Q f_empty = f(xbar)
+    for (int k = 1; k <= kmax; ++k) {
+      const size_t first = C.size();
+      for (const auto &c : all) {
+        if (c.k != k) continue;
+        bool pruned = false;
+        for (const auto &z : Z) {
+          CompState zc;
+          zc.k = k;
+          for (int q = 0; q < k; ++q) zc.dims[q] = c.dims[q];
+          pruned |= contains(zc, z.data(), (int)z.size());
+        }
+        if (pruned) continue;
+        CompState nc;
+        nc.k = c.k;
+        for (int q = 0; q < KMAX; ++q) nc.dims[q] = c.dims[q];
+        add_root(nc);
+        C.push_back(std::move(nc));
+      }
+      if (C.size() == first) break;
+      int rc = run_steps();
+      if (rc) return rc;
+      // quadrature of every candidate's component interpolant (u columns)
+      const int64_t ncand = (int64_t)(C.size() - first);
+      std::vector<int64_t> qoff(1, 0), qrow;
+      std::vector<double> qwt;
+      for (size_t s = first; s < C.size(); ++s) {
+        const CompState &c = C[s];
+        for (size_t r = 0; r < c.acc.size(); ++r) {
+          int ls = 0;
+          for (int q = 0; q < c.k; ++q) ls += c.lv[r * c.k + q];
+          qrow.push_back(c.build_row[r]);
+          qwt.push_back(std::ldexp(1.0, -ls));
+        }
+        qoff.push_back((int64_t)qrow.size());
+      }
+      std::vector<double> Q((size_t)(ncand * m));
+      {
+        int64_t *d_row = nullptr, *d_off = nullptr;
+        double *d_wt = nullptr, *d_q = nullptr;
+        hipError_t e = hipMalloc((void **)&d_row, sizeof(int64_t) * std::max<size_t>(qrow.size(), 1));
+        if (e == hipSuccess) e = hipMalloc((void **)&d_wt, sizeof(double) * std::max<size_t>(qwt.size(), 1));
+        if (e == hipSuccess) e = hipMalloc((void **)&d_off, sizeof(int64_t) * qoff.size());
+        if (e == hipSuccess) e = hipMalloc((void **)&d_q, sizeof(double) * Q.size());
+        if (e == hipSuccess && !qrow.empty())
+          e = hipMemcpy(d_row, qrow.data(), sizeof(int64_t) * qrow.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !qwt.empty())
+          e = hipMemcpy(d_wt, qwt.data(), sizeof(double) * qwt.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d_off, qoff.data(), sizeof(int64_t) * qoff.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+          hipLaunchKernelGGL(k_quadrature_rows, dim3((unsigned)ncand), dim3(256), 0, (hipStream_t)0, D.alpha, M2, m, m,
+                             d_row, d_wt, d_off, d_q);
+          e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemcpy(Q.data(), d_q, sizeof(double) * Q.size(), hipMemcpyDeviceToHost);
+        (void)hipFree(d_row);
+        (void)hipFree(d_wt);
+        (void)hipFree(d_off);
+        (void)hipFree(d_q);
+        if (e != hipSuccess) return hip_fail(e, "k_quadrature_rows");
+      }
+      auto norm2 = [&](const double *v) {
+        double s2 = 0.0;
+        for (int o = 0; o < m; ++o) s2 += v[o] * v[o];
+        return std::sqrt(s2);
+      };
+      const double denom = norm2(below.data());
+      std::vector<double> sum_k((size_t)m, 0.0);
+      for (int64_t j = 0; j < ncand; ++j) {
+        const CompState &c = C[first + (size_t)j];
+        DdsgCandidate rec{};
+        rec.k = c.k;
+        for (int q = 0; q < KMAX; ++q) rec.dims[q] = q < c.k ? c.dims[q] : -1;
+        rec.eta = std::numeric_limits<double>::quiet_NaN();
+        bool kept = true;
+        if (k >= 2 && P->eps_eta > 0.0) {
+          rec.eta = norm2(&Q[(size_t)(j * m)]) / denom;
+          kept = rec.eta > P->eps_eta;   // strict, as the text states
+        }
+        rec.kept = kept ? 1 : 0;
+        report.push_back(rec);
+        if (kept) {
+          keep.push_back((int)(first + (size_t)j));
+          for (int o = 0; o < m; ++o) sum_k[(size_t)o] += Q[(size_t)(j * m + o)];
+        } else {
+          Z.emplace_back(c.dims, c.dims + c.k);
+        }
+      }
+      const double rho = norm2(sum_k.data()) / denom;
+      report_rho.push_back(rho);
+      for (int o = 0; o < m; ++o) below[(size_t)o] += sum_k[(size_t)o];
+      if (P->eps_rho > 0.0 && !(rho > P->eps_rho)) break;   // continue only while rho > eps_rho
     }
   }
-  std::vector<double> weights((size_t)ncomp, 1.0);
+  // ---- assemble the model from the kept components ----
+  const int nkeep = (int)keep.size();
+  std::vector<double> weights((size_t)nkeep, 1.0);
   std::vector<double> c0 = f_anchor;
   if (P->form == 1) {
     // eq (4.2): b_i = sum over retained u containing i of (-1)^{|u|-|i|}; the
-    // retained family is the component list plus the empty set.
-    auto contains = [&](const CompState &u, const CompState &i) {
-      for (int q = 0; q < i.k; ++q) {
-        bool found = false;
-        for (int r = 0; r < u.k; ++r) found |= (u.dims[r] == i.dims[q]);
-        if (!found) return false;
-      }
-      return true;
-    };
+    // retained family is the kept components plus the empty set.
     int64_t b_empty = 1;
-    for (int u = 0; u < ncomp; ++u) b_empty += (C[u].k % 2) ? -1 : 1;
-    for (int s = 0; s < ncomp; ++s) {
+    for (int u : keep) b_empty += (C[u].k % 2) ? -1 : 1;
+    for (int s = 0; s < nkeep; ++s) {
+      const CompState &cs = C[keep[s]];
       int64_t b = 0;
-      for (int u = 0; u < ncomp; ++u)
-        if (contains(C[u], C[s])) b += ((C[u].k - C[s].k) % 2) ? -1 : 1;
+      for (int u : keep)
+        if (contains(C[u], cs.dims, cs.k)) b += ((C[u].k - cs.k) % 2) ? -1 : 1;
       weights[s] = (double)b;
     }
     for (int o = 0; o < m; ++o) c0[o] = (double)b_empty * f_anchor[o];
   }
-  std::vector<HostComponent> hc((size_t)ncomp);
-  for (int s = 0; s < ncomp; ++s) {
+  std::vector<HostComponent> hc((size_t)nkeep);
+  for (int s = 0; s < nkeep; ++s) {
+    const CompState &cs = C[keep[s]];
     HostComponent &h = hc[s];
-    h.k = C[s].k;
-    for (int q = 0; q < KMAX; ++q) h.dims[q] = C[s].dims[q];
+    h.k = cs.k;
+    for (int q = 0; q < KMAX; ++q) h.dims[q] = cs.dims[q];
     h.w = weights[s];
-    h.n = (int64_t)C[s].acc.size();
-    h.lv = C[s].lv.data();
-    h.ix = C[s].ix.data();
+    h.n = (int64_t)cs.acc.size();
+    h.lv = cs.lv.data();
+    h.ix = cs.ix.data();
     h.alpha = nullptr;
-    h.src_rows = C[s].build_row.data();
+    h.src_rows = cs.build_row.data();
   }
   DeviceAlphaSource src{D.alpha, M2, P->form == 0 ? m : 0};
-  return make_model(d, m, c0.data(), hc, out, &src);
+  int rc = make_model(d, m, c0.data(), hc, out, &src);
+  if (rc) return rc;
+  (*out)->ddsg = std::move(report);
+  (*out)->ddsg_rho = std::move(report_rho);
+  return HDMR_OK;
+}
+
+extern "C" int hdmr_build_report(const hdmr_model *model, int32_t *n_candidates, int32_t *n_orders, int32_t *cand_k,
+                                 int32_t *cand_dims, double *eta, uint8_t *kept, double *rho) {
+  clear_error();
+  if (!model || !n_candidates || !n_orders) return fail(HDMR_EINVAL, "hdmr_build_report: null argument");
+  *n_candidates = (int32_t)model->ddsg.size();
+  *n_orders = (int32_t)model->ddsg_rho.size();
+  for (size_t j = 0; j < model->ddsg.size(); ++j) {
+    const DdsgCandidate &c = model->ddsg[j];
+    if (cand_k) cand_k[j] = c.k;
+    if (cand_dims)
+      for (int q = 0; q < KMAX; ++q) cand_dims[j * KMAX + q] = c.dims[q];
+    if (eta) eta[j] = c.eta;
+    if (kept) kept[j] = c.kept;
+  }
+  if (rho)
+    for (size_t j = 0; j < model->ddsg_rho.size(); ++j) rho[j] = model->ddsg_rho[j];
+  return HDMR_OK;
+}
+
+extern "C" int hdmr_quadrature(const hdmr_model *model, double *q, double *total) {
+  clear_error();
+  if (!model || (!q && !total)) return fail(HDMR_EINVAL, "hdmr_quadrature: null argument");
+  int rc = set_device_of(model);
+  if (rc) return rc;
+  const int32_t nc = (int32_t)model->comps.size(), m = model->m;
+  std::vector<int64_t> off(1, 0), row;
+  std::vector<double> wt;
+  for (const Component &c : model->comps) {
+    for (int64_t r = c.row_begin; r < c.row_end; ++r) {
+      int ls = 0;
+      for (int k = 0; k < c.k; ++k) ls += model->lv_h[(size_t)(r * KMAX + k)];
+      row.push_back(r);
+      wt.push_back(std::ldexp(1.0, -ls));
+    }
+    off.push_back((int64_t)row.size());
+  }
+  std::vector<double> Q((size_t)std::max(nc, 1) * m, 0.0);
+  if (nc > 0) {
+    int64_t *d_row = nullptr, *d_off = nullptr;
+    double *d_wt = nullptr, *d_q = nullptr;
+    hipError_t e = hipMalloc((void **)&d_row, sizeof(int64_t) * std::max<size_t>(row.size(), 1));
+    if (e == hipSuccess) e = hipMalloc((void **)&d_wt, sizeof(double) * std::max<size_t>(wt.size(), 1));
+    if (e == hipSuccess) e = hipMalloc((void **)&d_off, sizeof(int64_t) * off.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&d_q, sizeof(double) * Q.size());
+    if (e == hipSuccess && !row.empty())
+      e = hipMemcpy(d_row, row.data(), sizeof(int64_t) * row.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !wt.empty()) e = hipMemcpy(d_wt, wt.data(), sizeof(double) * wt.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_off, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_quadrature_rows, dim3((unsigned)nc), dim3(256), 0, (hipStream_t)0, model->alpha, model->ms,
+                         0, m, d_row, d_wt, d_off, d_q);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(Q.data(), d_q, sizeof(double) * (size_t)nc * m, hipMemcpyDeviceToHost);
+    (void)hipFree(d_row);
+    (void)hipFree(d_wt);
+    (void)hipFree(d_off);
+    (void)hipFree(d_q);
+    if (e != hipSuccess) return hip_fail(e, "k_quadrature_rows");
+  }
+  if (q) std::memcpy(q, Q.data(), sizeof(double) * (size_t)nc * m);
+  if (total) {
+    for (int o = 0; o < m; ++o) {
+      double t = model->c0_h[(size_t)o];
+      for (int32_t c = 0; c < nc; ++c) t += model->comps[(size_t)c].w * Q[(size_t)c * m + o];
+      total[o] = t;
+    }
+  }
+  return HDMR_OK;
 }

@@ -73,6 +73,15 @@ struct Component {
   int32_t tup_begin, tup_end;    // global tuples
 };
 
+// One candidate index set of the adaptive build (Alg. 2): eta of eq (3.19)
+// (NaN when not tested) and whether it was kept.
+struct DdsgCandidate {
+  int32_t k;
+  int32_t dims[KMAX];
+  double eta;
+  uint8_t kept;
+};
+
 }  // namespace hdmr
 
 struct hdmr_model {
@@ -100,6 +109,9 @@ struct hdmr_model {
   std::vector<hdmr::PassTup> pass_tups_h;
   hdmr::PassTup *pass_tups = nullptr;
   int32_t max_pass_tups = 0;
+  // adaptive-build report (Alg. 2): candidates in build order, rho per order
+  std::vector<hdmr::DdsgCandidate> ddsg;
+  std::vector<double> ddsg_rho;
 
   hdmr::ModelView view() const {
     return hdmr::ModelView{tups, tab, alpha, c0, comp_tup, (int32_t)tups_h.size(), (int32_t)comps.size(), d, m, ms};

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <new>
 #include <vector>
 
 #include "hdmr_internal.h"
@@ -64,12 +65,22 @@ int hdmr_model_save(const hdmr_model *model, const char *path) {
   return HDMR_OK;
 }
 
-int hdmr_model_load(const char *path, hdmr_model **out) {
-  clear_error();
-  if (!path || !out) return fail(HDMR_EINVAL, "hdmr_model_load: null argument");
-  *out = nullptr;
+namespace {
+
+// Size of the open file (bytes), or -1.
+int64_t file_size(std::FILE *f) {
+  const long at = std::ftell(f);
+  if (at < 0 || std::fseek(f, 0, SEEK_END) != 0) return -1;
+  const long end = std::ftell(f);
+  if (std::fseek(f, at, SEEK_SET) != 0) return -1;
+  return end;
+}
+
+int model_load(const char *path, hdmr_model **out) {
   File f(std::fopen(path, "rb"));
   if (!f) return fail(HDMR_EINVAL, std::string("cannot open '") + path + "'");
+  const int64_t total = file_size(f.get());
+  if (total < 0) return fail(HDMR_EINVAL, std::string("cannot size '") + path + "'");
   char magic[8];
   uint32_t version = 0;
   int32_t d = 0, m = 0, nc = 0;
@@ -79,6 +90,11 @@ int hdmr_model_load(const char *path, hdmr_model **out) {
     return fail(HDMR_EUNSUPPORTED, "unsupported model file version");
   if (!get(f.get(), &d, 4) || !get(f.get(), &m, 4) || !get(f.get(), &nc, 4) || d < 1 || m < 1 || nc < 0)
     return fail(HDMR_EINVAL, "corrupt model file header");
+  // every count is checked against the bytes left in the file before any
+  // buffer is sized from it (no overflow: each factor is bounded first)
+  int64_t left = total - std::ftell(f.get());
+  if ((int64_t)m > left / 8) return fail(HDMR_EINVAL, "corrupt model file header (m exceeds the file)");
+  if ((int64_t)nc > left / 20) return fail(HDMR_EINVAL, "corrupt model file header (components exceed the file)");
   std::vector<double> c0((size_t)m);
   if (!get(f.get(), c0.data(), 8 * (size_t)m)) return fail(HDMR_EINVAL, "truncated model file");
   std::vector<int32_t> offsets(1, 0), dims;
@@ -92,9 +108,12 @@ int hdmr_model_load(const char *path, hdmr_model **out) {
     int64_t n = 0;
     if (!get(f.get(), &k, 4) || k < 1 || k > KMAX) return fail(HDMR_EINVAL, "corrupt component header");
     int32_t cd[KMAX];
-    if (!get(f.get(), cd, 4 * (size_t)k) || !get(f.get(), &w, 8) || !get(f.get(), &n, 8) || n < 0 ||
-        n > ((int64_t)1 << 40))
+    if (!get(f.get(), cd, 4 * (size_t)k) || !get(f.get(), &w, 8) || !get(f.get(), &n, 8) || n < 0)
       return fail(HDMR_EINVAL, "corrupt component header");
+    left = total - std::ftell(f.get());
+    // a row takes k level bytes, 4 k index bytes and 8 m surplus bytes
+    const int64_t row_bytes = 5 * (int64_t)k + 8 * (int64_t)m;
+    if (n > left / row_bytes) return fail(HDMR_EINVAL, "corrupt component header (rows exceed the file)");
     dims.insert(dims.end(), cd, cd + k);
     offsets.push_back(offsets.back() + k);
     npts.push_back(n);
@@ -109,6 +128,21 @@ int hdmr_model_load(const char *path, hdmr_model **out) {
   }
   return hdmr_model_from_surpluses(d, m, c0.data(), nc, offsets.data(), dims.data(), npts.data(), lv.data(),
                                    ix.data(), al.data(), weights.data(), out);
+}
+
+}  // namespace
+
+int hdmr_model_load(const char *path, hdmr_model **out) {
+  clear_error();
+  if (!path || !out) return fail(HDMR_EINVAL, "hdmr_model_load: null argument");
+  *out = nullptr;
+  try {
+    return model_load(path, out);
+  } catch (const std::bad_alloc &) {
+    return fail(HDMR_ENOMEM, "hdmr_model_load: host allocation failed");
+  } catch (...) {
+    return fail(HDMR_EINVAL, "hdmr_model_load: corrupt model file");
+  }
 }
 
 }  // extern "C"

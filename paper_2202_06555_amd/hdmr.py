@@ -31,7 +31,7 @@ EXPORTS = (
     "hdmr_init", "asg_build_components", "hdmr_model_from_surpluses", "hdmr_eval", "hdmr_eval_grad",
     "hdmr_get_info", "hdmr_export_component", "hdmr_free", "hdmr_last_error", "hdmr_eval_stats",
     "hdmr_timing_enable", "hdmr_timing_read", "hdmr_model_save", "hdmr_model_load", "hdmr_eval_batched",
-    "hdmr_eval_noalloc",
+    "hdmr_eval_noalloc", "hdmr_model_naive", "hdmr_build_report", "hdmr_quadrature",
     # include/hdmr_surrogate.h
     "mlp_param_count", "mlp_create", "mlp_get_params", "mlp_set_standardization", "mlp_fit_standardization",
     "mlp_get_standardization", "mlp_forward", "mlp_loss_grads", "mlp_train", "mlp_free", "hdmr_model_select",
@@ -82,6 +82,9 @@ def lib():
                 "hdmr_model_from_surpluses": [i32, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp],
                 "hdmr_eval": [vp, vp, i64, vp, i32, i32, vp],
                 "hdmr_eval_noalloc": [vp, vp, i64, vp, i32, i32, vp],
+                "hdmr_model_naive": [vp, vp, vp],
+                "hdmr_build_report": [vp, vp, vp, vp, vp, vp, vp, vp],
+                "hdmr_quadrature": [vp, vp, vp],
                 "hdmr_eval_grad": [vp, vp, i64, vp, vp, i32, vp],
                 "hdmr_get_info": [vp, vp],
                 "hdmr_eval_stats": [vp, vp, i64, vp, vp, vp],
@@ -181,12 +184,14 @@ def hdmr_model_from_surpluses(model) -> Model:
 
 
 def asg_build_components(d, m, anchor, fn, comps=None, max_order=2, max_level=7, level_rule=0, refine_rule=0,
-                         eps_gamma=1e-4, form=0) -> Model:
+                         eps_gamma=1e-4, form=0, eps_eta=0.0, eps_rho=0.0) -> Model:
     """Build a model on the device.  ``fn`` is a Python callable f(X)->Y or a
-    (c_function_address, user_pointer) pair with the hdmr_fn signature."""
+    (c_function_address, user_pointer) pair with the hdmr_fn signature.
+    eps_eta / eps_rho > 0 apply the Alg. 2 criteria (hdmr_build_report)."""
     p = _BuildParams()
     p.d, p.m, p.max_order, p.max_level = int(d), int(m), int(max_order), int(max_level)
     p.level_rule, p.refine_rule, p.eps_gamma, p.form = int(level_rule), int(refine_rule), float(eps_gamma), int(form)
+    p.eps_eta, p.eps_rho = float(eps_eta), float(eps_rho)
     anc = np.ascontiguousarray(anchor, dtype=np.float64)
     p.anchor = anc.ctypes.data
     keep = [anc]
@@ -243,6 +248,44 @@ def hdmr_eval(model: Model, points, values=None, precision=PLAIN_FP64, stream=No
     _check(lib().hdmr_eval(model.handle, _dev(points, "points", (n, inf["d"])), n,
                            _dev(values, "values", (n, inf["m"])), inf["m"], int(precision), _stream_ptr(stream)))
     return values
+
+
+def hdmr_model_naive(model: Model, f_anchor) -> Model:
+    """The eq (3.16) term-by-term model of an eq (4.2)-form model (f_anchor =
+    f(xbar), m values)."""
+    import numpy as np
+    fa = np.ascontiguousarray(f_anchor, dtype=np.float64)
+    h = ctypes.c_void_p()
+    _check(lib().hdmr_model_naive(model.handle, fa.ctypes.data, ctypes.byref(h)))
+    return Model(h.value)
+
+
+def hdmr_build_report(model: Model):
+    """Alg. 2 report of an adaptive build: dict with 'candidates' (index-set
+    tuples in build order), 'eta' (NaN where not tested), 'kept' (bool) and
+    'rho' (one per expansion order built)."""
+    import numpy as np
+    nc, no = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().hdmr_build_report(model.handle, ctypes.byref(nc), ctypes.byref(no), None, None, None, None, None))
+    k = np.zeros(nc.value, np.int32)
+    dims = np.zeros((nc.value, 4), np.int32)
+    eta = np.zeros(nc.value)
+    kept = np.zeros(nc.value, np.uint8)
+    rho = np.zeros(no.value)
+    _check(lib().hdmr_build_report(model.handle, ctypes.byref(nc), ctypes.byref(no), k.ctypes.data, dims.ctypes.data,
+                                   eta.ctypes.data, kept.ctypes.data, rho.ctypes.data))
+    cands = [tuple(int(v) for v in dims[j, :k[j]]) for j in range(nc.value)]
+    return {"candidates": cands, "eta": eta, "kept": kept.astype(bool), "rho": rho}
+
+
+def hdmr_quadrature(model: Model):
+    """(per-component quadratures (ncomp, m) of eq (3.7), total c0 + sum w_S Q u_S (m,))."""
+    import numpy as np
+    inf = hdmr_get_info(model)
+    q = np.zeros((max(inf["n_components"], 1), inf["m"]))
+    t = np.zeros(inf["m"])
+    _check(lib().hdmr_quadrature(model.handle, q.ctypes.data, t.ctypes.data))
+    return q[:inf["n_components"]], t
 
 
 def hdmr_eval_noalloc(model: Model, points, values, precision=PLAIN_FP64, stream=None):

@@ -83,6 +83,33 @@ def test_model_load_rejects_bad_files(tmp_path):
     assert e.value.code == hd.hdmr.HDMR_EINVAL
 
 
+def test_model_load_rejects_oversized_headers(tmp_path):
+    # counts in the header or a component header that exceed the file are
+    # rejected before any buffer is sized from them (no allocation failure,
+    # no exception through the C ABI)
+    import struct
+    import paper_2202_06555_amd as hd
+    head = b"HDMRASG1" + struct.pack("<I", 1)
+    cases = {
+        "huge_m.hdmr": head + struct.pack("<iii", 4, 2 ** 30, 1) + b"\0" * 64,
+        "huge_nc.hdmr": head + struct.pack("<iii", 4, 1, 2 ** 31 - 1) + b"\0" * 64,
+        # one component whose row count would overflow n * m in 64 bits
+        "huge_rows.hdmr": (head + struct.pack("<iii", 4, 3, 1) + struct.pack("<3d", 0, 0, 0) +
+                           struct.pack("<i", 2) + struct.pack("<ii", 0, 1) + struct.pack("<d", 1.0) +
+                           struct.pack("<q", 2 ** 62) + b"\0" * 64),
+        "negative_rows.hdmr": (head + struct.pack("<iii", 4, 3, 1) + struct.pack("<3d", 0, 0, 0) +
+                               struct.pack("<i", 2) + struct.pack("<ii", 0, 1) + struct.pack("<d", 1.0) +
+                               struct.pack("<q", -5)),
+    }
+    for name, data in cases.items():
+        f = tmp_path / name
+        f.write_bytes(data)
+        with pytest.raises(hd.HdmrError) as e:
+            hd.hdmr_model_load(str(f))
+        assert e.value.code == hd.hdmr.HDMR_EINVAL, name
+        assert "corrupt" in str(e.value), name
+
+
 def test_surrogate_host_validation():
     import paper_2202_06555_amd as hd
     from paper_2202_06555_amd import surrogate as sg

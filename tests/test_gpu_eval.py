@@ -145,47 +145,64 @@ def test_gradient_parity(hd):
         np.testing.assert_allclose(G[ok], rg[ok], rtol=0, atol=TOL * scale)
 
 
-def test_c2_full_size_sampled(hd):
-    # d=20, 210 components, adaptive L=7 eps=1e-4, m=11, 1e6 next-state points
+def test_c2_full_size_all_points(hd):
+    # d=20, 210 components, adaptive L=7 eps=1e-4, m=11: all 1e6 next-state
+    # points against the oracle
     import torch
-    cfg = ws.config("c2")
-    tf = ws.test_function_for(cfg)
-    model, _ = oracle.build_model(cfg["comps"], cfg["d"], cfg["m"], cfg["anchor"], (tf.c_fn, tf.c_user),
-                                  max_level=cfg["max_level"], eps_gamma=cfg["eps_gamma"])
-    X = ws.points_for(cfg)
-    gm = hd.hdmr_model_from_surpluses(model)
+    import _fullsize as fs
+    X = fs.c2_points()
+    gm = hd.hdmr_model_from_surpluses(fs.c2_model())
     Y = hd.hdmr_eval(gm, _dev(X))
     torch.cuda.synchronize()
-    idx = np.random.default_rng(0).choice(X.shape[0], 3000, replace=False)
-    idx = np.concatenate([idx, np.arange(50), np.arange(X.shape[0] - 50, X.shape[0])])
-    ref = oracle.evaluate(model, X[idx])
-    err = np.abs(Y.cpu().numpy()[idx] - ref).max()
-    print("c2 sampled max |err| = %.3e" % err)
+    err = np.abs(Y.cpu().numpy() - fs.c2_reference()).max()
+    print("c2 all %d points max |err| = %.3e" % (X.shape[0], err))
     assert err <= TOL
 
 
+def test_non_dyadic_weights(hd):
+    # component weights that are not exact in FP32 (0.1, 1/3, -2.7, ...) on
+    # 20000 points (the cell-sorted path's size range) on both kernels, and the
+    # mixed path's per-output bar on the same model
+    model = ws.synthetic_regular_model(d=5, m=7, order=2, ell=5, seed=9)
+    wts = np.array([0.1, 1.0 / 3.0, -2.7, 1e-3, 7.25, -1.0 / 7.0, np.pi, 2.0 ** -30 + 1.0])
+    model["weights"] = wts[np.arange(len(model["comps"])) % len(wts)]
+    rng = np.random.default_rng(19)
+    X = np.vstack([_special_points(5, rng, 200), rng.random((20000, 5))])
+    gm, Y = _eval(hd, model, X)
+    ref = oracle.evaluate(model, X)
+    ok = ~np.isnan(X).any(axis=1)
+    err = np.abs(Y[ok] - ref[ok]).max()
+    print("non-dyadic weights: max |err| = %.3e" % err)
+    assert err <= TOL
+    import _fullsize as fs
+    Ym = hd.hdmr_eval(gm, _dev(X), precision=hd.MIXED).cpu().numpy()
+    rel = fs.per_output_rel(Ym[ok], ref[ok])
+    print("non-dyadic weights, mixed: worst per-output %.3e" % rel)
+    assert rel <= 1e-6
+
+
 def test_c2_full_size_gradient_sampled(hd, eval_path):
-    # values and gradients at 1e6 next-state points, checked on 1000 sampled points
+    # values and gradients at all 1e6 next-state points; values checked at
+    # every point, gradients on 1e5 sampled points
     if eval_path == "gather":
         pytest.skip("the full-size gradient runs once, on the path the library picks by size")
     import os
     import torch
+    import _fullsize as fs
     os.environ.pop("HDMR_EVAL_PATH", None)
-    cfg = ws.config("c2")
-    tf = ws.test_function_for(cfg)
-    model, _ = oracle.build_model(cfg["comps"], cfg["d"], cfg["m"], cfg["anchor"], (tf.c_fn, tf.c_user),
-                                  max_level=cfg["max_level"], eps_gamma=cfg["eps_gamma"])
-    X = ws.points_for(cfg)
+    model = fs.c2_model()
+    X = fs.c2_points()
     gm = hd.hdmr_model_from_surpluses(model)
     Y, G = hd.hdmr_eval_grad(gm, _dev(X))
     torch.cuda.synchronize()
-    idx = np.concatenate([np.random.default_rng(5).choice(X.shape[0], 1000, replace=False), np.arange(20)])
+    assert np.abs(Y.cpu().numpy() - fs.c2_reference()).max() <= TOL
+    idx = fs.sample_rows(X.shape[0], 100_000, 5)
     ry, rg = oracle.gradient(model, X[idx])
     np.testing.assert_allclose(Y.cpu().numpy()[idx], ry, rtol=0, atol=TOL)
     g = G.cpu().numpy()[idx]
     scale = max(1.0, np.abs(rg).max())
     err = np.abs(g - rg).max()
-    print("c2 gradient sampled max |err| = %.3e (scale %.1f)" % (err, scale))
+    print("c2 gradient on %d sampled points max |err| = %.3e (scale %.1f)" % (len(idx), err, scale))
     assert err <= TOL * scale
 
 
@@ -201,4 +218,5 @@ def test_four_dim_components(hd):
     Ym = hd.hdmr_eval(gm, _dev(X), precision=hd.MIXED).cpu().numpy()
     ref = oracle.evaluate(model, X)
     ok = ~np.isnan(X).any(axis=1)
-    assert np.linalg.norm(Ym[ok] - ref[ok]) <= 1e-6 * np.linalg.norm(ref[ok])
+    import _fullsize as fs
+    assert fs.per_output_rel(Ym[ok], ref[ok]) <= 1e-6

@@ -1,9 +1,10 @@
 """GPU parity of the mixed-precision evaluation (FP32 basis and surpluses,
 split-BF16 matrix-core products with FP32 accumulation per pass, FP64
 accumulation across components and of c0) against the FP64 oracle, through
-the C ABI.  Bar: normwise relative error ||Y - Y_oracle||_F / ||Y_oracle||_F
-<= 1e-6 on every component-form model; eq (4.2)-form models, whose weighted
-terms cancel, are held to 1e-6 relative to the norm of the summed |terms|.
+the C ABI.  Bar, per output o: max_p |Y_po - Y_oracle,po| / max_p |Y_oracle,po|
+<= 1e-6 on every component-form model (the normwise error is printed beside
+it); eq (4.2)-form models, whose weighted terms cancel, are held per output to
+1e-6 relative to max_p of the summed |terms|.
 NaN and out-of-domain points behave as in the plain path."""
 import numpy as np
 import pytest
@@ -13,7 +14,7 @@ import workloads.synth as ws
 
 pytestmark = pytest.mark.gpu
 
-NORMWISE = 1e-6
+BAR = 1e-6
 
 
 @pytest.fixture(scope="module")
@@ -39,6 +40,13 @@ def _normwise(Y, ref):
     return float(np.linalg.norm(Y - ref) / max(np.linalg.norm(ref), 1e-300))
 
 
+def _per_output(Y, ref, scale=None):
+    """max over outputs of max_p |Y - ref| / max_p |scale| (scale = ref)."""
+    scale = ref if scale is None else scale
+    Y, ref, scale = (np.asarray(a).reshape(a.shape[0], -1) for a in (Y, ref, scale))
+    return float((np.abs(Y - ref).max(axis=0) / np.maximum(np.abs(scale).max(axis=0), 1e-300)).max())
+
+
 def _special_points(d, rng, n):
     X = rng.random((n, d))
     X[0] = 0.0
@@ -58,9 +66,9 @@ def test_c1_mixed(hd):
     gm = hd.hdmr_model_from_surpluses(model)
     Y = _mixed(hd, gm, X)
     ref = oracle.evaluate(model, X)
-    nw = _normwise(Y, ref)
-    print("c1 mixed normwise %.3e, max |err| %.3e" % (nw, np.abs(Y - ref).max()))
-    assert nw <= NORMWISE
+    nw, po = _normwise(Y, ref), _per_output(Y, ref)
+    print("c1 mixed normwise %.3e, worst per-output %.3e, max |err| %.3e" % (nw, po, np.abs(Y - ref).max()))
+    assert po <= BAR
 
 
 @pytest.mark.parametrize("m", [1, 3, 16, 17, 51, 64, 65, 130, 256])
@@ -71,10 +79,9 @@ def test_mixed_output_widths(hd, m):
     gm = hd.hdmr_model_from_surpluses(model)
     Y = _mixed(hd, gm, X)
     ref = oracle.evaluate(model, X)
-    assert _normwise(Y, ref) <= NORMWISE
-    # every output column on its own
-    for o in range(m):
-        assert _normwise(Y[:, o], ref[:, o]) <= 10 * NORMWISE
+    po = _per_output(Y, ref)
+    print("m=%d mixed worst per-output %.3e" % (m, po))
+    assert po <= BAR
 
 
 def test_mixed_nan_outside_and_empty(hd):
@@ -86,16 +93,16 @@ def test_mixed_nan_outside_and_empty(hd):
     ref = oracle.evaluate(model, X)
     assert np.all(np.isnan(Y[0]))
     np.testing.assert_array_equal(Y[1], ref[1])      # all basis functions vanish: exactly c0
-    assert _normwise(Y[2:], ref[2:]) <= NORMWISE
+    assert _per_output(Y[2:], ref[2:]) <= BAR
     empty = torch.empty((0, 4), dtype=torch.float64, device="cuda:0")
     assert hd.hdmr_eval(gm, empty, precision=hd.MIXED).shape == (0, 3)
 
 
 def test_mixed_adaptive_three_dim_and_paper_form(hd):
-    """Component form (u_S surpluses, unit weights): normwise 1e-6.  The
+    """Component form (u_S surpluses, unit weights): the per-output bar.  The
     eq (4.2) form sums integer-weighted cut functions b_S g_S that cancel
     (|F| far below sum |b_S g_S|), and FP32 rounding error scales with the
-    summed terms; its bar is 1e-6 relative to ||sum of |terms|||."""
+    summed terms; its bar is 1e-6 per output relative to the summed |terms|."""
     cfg = ws.config("c2", d=5, m=7, npairs="all", max_level=8)
     tf = ws.test_function_for(cfg)
     comps = ws.all_components(5, 3)
@@ -106,27 +113,25 @@ def test_mixed_adaptive_three_dim_and_paper_form(hd):
         gm = hd.hdmr_model_from_surpluses(model)
         Y = _mixed(hd, gm, X)
         ref, mag = oracle.evaluate(model, X, with_abs=True)
-        nw = _normwise(Y, ref)
-        rel_terms = float(np.linalg.norm(Y - ref) / np.linalg.norm(mag))
-        print("adaptive 3-D %s form: mixed normwise %.3e, relative to summed terms %.3e" % (form, nw, rel_terms))
+        nw, po = _normwise(Y, ref), _per_output(Y, ref)
+        rel_terms = _per_output(Y, ref, scale=mag)
+        print("adaptive 3-D %s form: mixed normwise %.3e, worst per-output %.3e, relative to summed terms %.3e" %
+              (form, nw, po, rel_terms))
         if form == "component":
-            assert nw <= NORMWISE
-        assert rel_terms <= NORMWISE
+            assert po <= BAR
+        assert rel_terms <= BAR
 
 
-def test_mixed_c2_full_size_sampled(hd):
+def test_mixed_c2_full_size_all_points(hd):
+    # all 1e6 next-state points of the d=20 workload against the oracle
     import torch
-    cfg = ws.config("c2")
-    tf = ws.test_function_for(cfg)
-    model, _ = oracle.build_model(cfg["comps"], cfg["d"], cfg["m"], cfg["anchor"], (tf.c_fn, tf.c_user),
-                                  max_level=cfg["max_level"], eps_gamma=cfg["eps_gamma"])
-    X = ws.points_for(cfg)
-    gm = hd.hdmr_model_from_surpluses(model)
+    import _fullsize as fs
+    X = fs.c2_points()
+    gm = hd.hdmr_model_from_surpluses(fs.c2_model())
     Y = hd.hdmr_eval(gm, _dev(X), precision=hd.MIXED)
     torch.cuda.synchronize()
-    idx = np.random.default_rng(0).choice(X.shape[0], 3000, replace=False)
-    idx = np.concatenate([idx, np.arange(50), np.arange(X.shape[0] - 50, X.shape[0])])
-    ref = oracle.evaluate(model, X[idx])
-    nw = _normwise(Y.cpu().numpy()[idx], ref)
-    print("c2 mixed sampled normwise %.3e" % nw)
-    assert nw <= NORMWISE
+    Y = Y.cpu().numpy()
+    ref = fs.c2_reference()
+    nw, po = _normwise(Y, ref), _per_output(Y, ref)
+    print("c2 mixed, all points: normwise %.3e, worst per-output %.3e" % (nw, po))
+    assert po <= BAR

@@ -144,3 +144,33 @@ def test_gradient_at_edges_is_right_derivative():
         else:
             one_sided = (oracle.evaluate(model, X) - oracle.evaluate(model, X - [[h, 0]])) / h
         np.testing.assert_allclose(G[:, 0, :], one_sided, rtol=0, atol=1e-5)
+
+
+def test_summed_magnitudes_closed_form():
+    # Yabs = |c0| + sum_S sum_j |w_S alpha_j phi_j(x)|: with every surplus,
+    # weight and c0 of one sign the terms cannot cancel, so Yabs = |F|
+    # exactly (up to rounding) in both modes; with mixed signs Yabs >= |F|
+    # and Yabs - |F| is twice the mass of the minority-sign terms, checked
+    # against a direct sum of positive and negative parts.
+    rng = np.random.default_rng(31)
+    model = ws.synthetic_regular_model(d=4, m=3, order=2, ell=4, seed=31)
+    X = np.vstack([_special_points(4, rng), rng.random((500, 4))])
+    ok = ~np.isnan(X).any(axis=1)
+    for sign in (1.0, -1.0):
+        mdl = dict(model)
+        mdl["alpha"] = [sign * np.abs(a) for a in model["alpha"]]
+        mdl["c0"] = sign * np.abs(model["c0"])
+        mdl["weights"] = np.full(len(model["comps"]), 0.75)
+        for mode in ("brute", "levelwise"):
+            Y, A = oracle.evaluate(mdl, X, mode=mode, with_abs=True)
+            np.testing.assert_allclose(A[ok], np.abs(Y[ok]), rtol=1e-14, atol=1e-15)
+    # mixed signs: positive and negative parts evaluated as separate models
+    pos, neg = dict(model), dict(model)
+    pos["alpha"] = [np.maximum(a, 0.0) for a in model["alpha"]]
+    neg["alpha"] = [np.minimum(a, 0.0) for a in model["alpha"]]
+    pos["c0"] = np.maximum(model["c0"], 0.0)
+    neg["c0"] = np.minimum(model["c0"], 0.0)
+    Yp = oracle.evaluate(pos, X)
+    Yn = oracle.evaluate(neg, X)
+    _, A = oracle.evaluate(model, X, with_abs=True)
+    np.testing.assert_allclose(A[ok], Yp[ok] - Yn[ok], rtol=1e-13, atol=1e-15)

@@ -135,3 +135,36 @@ def test_test_function_decomposition_recovered():
     Z[:, 1] = np.linspace(0, 1, 50)
     Z[:, 3] = np.linspace(1, 0, 50)
     np.testing.assert_allclose(tf(Z), tf.direct(Z), rtol=0, atol=1e-13)
+
+
+def test_naive_eq_3_16_regroups_to_eq_4_2_and_telescopes():
+    # eq (3.16) summed term by term equals its regrouping a(x)^T b of eq (4.2)
+    # (the same signed terms collected per cut function), and at the nodes of
+    # regular (projection-closed) grids on the anchor lines it reproduces f
+    # exactly (eq (2.2.6)); a family that is not closed under subsets is refused
+    d, m = 5, 3
+    pairs = [(0, 1), (1, 3), (2, 4)]
+    tf = ws.TestFunction(d, m, pairs, seed=4)
+    comps = ws.all_components(d, 2)
+    model, info = oracle.build_model(comps, d, m, tf.ref, (tf.c_fn, tf.c_user), max_level=4, level_rule=1,
+                                     eps_gamma=-1.0, form="paper")
+    rng = np.random.default_rng(8)
+    X = rng.random((300, d))
+    naive = oracle.evaluate_naive(model, X, info["f_anchor"])
+    regrouped, mag = oracle.evaluate(model, X, with_abs=True)
+    np.testing.assert_allclose(naive, regrouped, rtol=0, atol=1e-13 * max(1.0, np.abs(mag).max()))
+    for S, lv, ix in zip(model["comps"], model["levels"], model["indices"]):
+        Xn = np.tile(tf.ref, (lv.shape[0], 1))
+        Xn[:, list(S)] = oracle.node_coordinates(lv, ix)
+        np.testing.assert_allclose(oracle.evaluate_naive(model, Xn, info["f_anchor"]), tf(Xn), rtol=0, atol=1e-12)
+    # a planted mistake: one sign flipped in the term sum breaks the equality
+    bad = dict(model)
+    bad["alpha"] = list(model["alpha"])
+    bad["alpha"][0] = -bad["alpha"][0]
+    assert np.abs(oracle.evaluate_naive(bad, X, info["f_anchor"]) - regrouped).max() > 1e-6
+    sub = dict(model)
+    keep = [s for s, S in enumerate(comps) if S != (1,)]
+    for key in ("comps", "levels", "indices", "alpha"):
+        sub[key] = [model[key][s] for s in keep]
+    with pytest.raises(ValueError):
+        oracle.evaluate_naive(sub, X, info["f_anchor"])
