@@ -77,7 +77,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device copy first (scale reference for HBM counters)")
-    ap.add_argument("--workload", choices=["eval", "batched", "surrogate", "grad", "naive"], default="eval",
+    ap.add_argument("--workload", choices=["eval", "batched", "surrogate", "grad", "naive", "irbc"], default="eval",
                     help="eval: the metric workload (default); batched: many models in one call; "
                          "surrogate: the learned part on the d=300 workload; grad: values and gradients "
                          "on the d=20 workload")
@@ -98,6 +98,8 @@ def main():
         return bench_grad(args)
     if args.workload == "naive":
         return bench_naive(args)
+    if args.workload == "irbc":
+        return bench_irbc(args)
 
     import torch
 
@@ -435,6 +437,61 @@ def bench_naive(args):
                    "paper_context": "the paper measures the vectorised form about 2.8x faster than the naive one "
                                     "on CPUs (smooth IRBC model, Sec. 5.1)"},
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench_irbc(args):
+    """The expectation operator of time iteration on the smooth IRBC model
+    (Sec. 2.1): N = 50 countries (d = 100, m = 51), a synthetic previous policy
+    built on the device (100 one-dim + 50 two-dim components, L = 7,
+    eps_gamma = 1e-5), 40000 states with candidate choices; every state's 102
+    monomial-rule next states go through hdmr_eval (4.08e6 evaluations per
+    call), then the Euler and resource residuals are assembled."""
+    import numpy as np
+    import torch
+
+    import paper_2202_06555_amd as hd
+    from paper_2202_06555_amd import irbc
+    import workloads.synth as ws
+
+    hd.hdmr_init(0)
+    N, n = 50, 40_000
+    p = ws.irbc_params(N)
+    g = ws.IrbcGuess(N)
+    t0 = time.time()
+    gm = hd.asg_build_components(g.d, g.m, g.anchor, g, comps=g.components(), max_level=7, eps_gamma=1e-5)
+    build_s = time.time() - t0
+    X, C = ws.irbc_states(n, N, seed=11)
+    Xd, Cd = torch.from_numpy(X).to("cuda:0"), torch.from_numpy(C).to("cuda:0")
+    R = torch.empty((n, N + 1), dtype=torch.float64, device="cuda:0")
+    t = _timed(lambda: irbc.irbc_residuals(gm, p, Xd, Cd, residuals=R), args.steps, args.warmup)
+    Q = 2 * (N + 1)
+    Xn = torch.rand((n * Q, 2 * N), dtype=torch.float64, device="cuda:0")
+    Yn = torch.empty((n * Q, N + 1), dtype=torch.float64, device="cuda:0")
+    t_eval = _timed(lambda: hd.hdmr_eval(gm, Xn, Yn), args.steps, args.warmup)
+    out = {
+        "metric": "smooth-IRBC FOC residual evaluations (states/s) at N=50 (d=100, m=51)",
+        "value": n / t, "unit": "states/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "N=50 countries, synthetic previous policy (150 components, L=7, eps_gamma=1e-5), "
+                               "%d states, degree-3 monomial rule (%d nodes)" % (n, Q),
+                   "policy_rows": hd.hdmr_get_info(gm)["n_rows"], "build_s_untimed": build_s,
+                   "next_state_evals_per_s": n * Q * (N + 1) / t,
+                   "hdmr_eval_ms_same_count_uniform_points": t_eval * 1e3},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import irbc as oirbc
+        model, _ = oracle.build_model(g.components(), g.d, g.m, g.anchor, g, max_level=7, eps_gamma=1e-5)
+        k = 40
+        t0 = time.perf_counter()
+        Ro, _ = oirbc.residuals(model, p, X[:k], C[:k])
+        tc = time.perf_counter() - t0
+        Rg = R[:k].cpu().numpy()
+        out["error_vs_oracle"] = {"max_abs": float(np.abs(Rg - Ro).max()), "states": k}
+        out["cpu_baseline"] = {"value": k / tc, "unit": "states/s", "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": "first %d states" % k}
     print(json.dumps(out), flush=True)
 
 

@@ -32,6 +32,8 @@ EXPORTS = (
     "hdmr_get_info", "hdmr_export_component", "hdmr_free", "hdmr_last_error", "hdmr_eval_stats",
     "hdmr_timing_enable", "hdmr_timing_read", "hdmr_model_save", "hdmr_model_load", "hdmr_eval_batched",
     "hdmr_eval_noalloc", "hdmr_model_naive", "hdmr_build_report", "hdmr_quadrature",
+    # include/hdmr_irbc.h
+    "irbc_residuals", "irbc_solve", "irbc_euler_errors", "irbc_time_step",
     # include/hdmr_surrogate.h
     "mlp_param_count", "mlp_create", "mlp_get_params", "mlp_set_standardization", "mlp_fit_standardization",
     "mlp_get_standardization", "mlp_forward", "mlp_loss_grads", "mlp_train", "mlp_free", "hdmr_model_select",

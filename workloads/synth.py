@@ -356,3 +356,54 @@ def points_for(cfg, n=None, seed=None):
 
 def test_function_for(cfg):
     return TestFunction(cfg["d"], cfg["m"], cfg["pairs"], cfg["seed"], ref=cfg["anchor"])
+
+
+# --------------------------------------------------------------------------
+# smooth IRBC workload (Sec. 2.1, Table 1)
+# --------------------------------------------------------------------------
+
+def irbc_params(N, sigma=0.01, gamma_span=0.75):
+    """Table 1 of the paper for N countries, with the readings used here:
+    gamma_j = 0.25 + 0.75 (j - 1) / (N - 1) (the table's lower end is garbled;
+    0.25 gives the usual range [0.25, 1]) and the state box
+    a in [0.8, 1.2]^N, k in [0.8, 1.2]^N."""
+    return dict(N=int(N), beta=0.99, alpha=0.36, delta=0.01, sigma=float(sigma), rho=0.95, phi=0.5,
+                gamma_lo=0.25, gamma_span=float(gamma_span), a_lo=0.8, a_hi=1.2, k_lo=0.8, k_hi=1.2)
+
+
+class IrbcGuess:
+    """A smooth synthetic policy (k_{t+1}, lambda_t) over the normalised state
+    box, the stand-in for a previous time-iteration iterate (the paper
+    publishes no policies):
+      k'_j   = k_j (1 - 0.01) + 0.01 + 0.05 (a_j - 1) + 0.02 (a_j - 1)(k_j - 1)
+      lambda = 1.2 (1 - 0.3 mean_j (a_j - 1) + 0.2 mean_j (k_j - 1)),
+    with a_j, k_j the box coordinates of x (a = 0.8 + 0.4 x_j, k = 0.8 + 0.4
+    x_{N+j}).  Its cut-HDMR components are the one-dimensional ones and the
+    pairs (j, N + j)."""
+
+    def __init__(self, N):
+        self.N = int(N)
+        self.d, self.m = 2 * self.N, self.N + 1
+        self.anchor = np.full(self.d, 0.5)
+
+    def components(self):
+        return [(q,) for q in range(self.d)] + [(j, self.N + j) for j in range(self.N)]
+
+    def __call__(self, X):
+        X = np.atleast_2d(np.asarray(X, dtype=np.float64))
+        N = self.N
+        a = 0.8 + 0.4 * X[:, :N]
+        k = 0.8 + 0.4 * X[:, N:]
+        Y = np.empty((X.shape[0], N + 1))
+        Y[:, :N] = k * 0.99 + 0.01 + 0.05 * (a - 1.0) + 0.02 * (a - 1.0) * (k - 1.0)
+        Y[:, N] = 1.2 * (1.0 - 0.3 * (a - 1.0).mean(axis=1) + 0.2 * (k - 1.0).mean(axis=1))
+        return Y
+
+
+def irbc_states(n, N, seed):
+    """n states uniform on the normalised box [0,1]^{2N} and choices near the
+    synthetic policy there (k' and lambda scaled by 1 + 0.02 u, u ~ U[-1,1])."""
+    rng = np.random.default_rng(seed)
+    X = rng.random((n, 2 * N))
+    C = IrbcGuess(N)(X) * (1.0 + 0.02 * rng.uniform(-1.0, 1.0, size=(n, N + 1)))
+    return X, C
