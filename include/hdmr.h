@@ -191,13 +191,16 @@ int hdmr_eval_grad(const hdmr_model *model, const double *points, int64_t n, dou
  * units of a few points taken from a device queue, heaviest models first),
  * replayed from a hipGraph cached per batch signature (models, points,
  * values, n, precision); models with n >= 16384 are first timed on the call's
- * data on each candidate path (persistent gather, cell-sorted with two
- * contraction tile shapes) and the fastest is kept per (model, size bucket
- * floor(log2 n), precision) -- the call that measures leaves correct values.
- * Gather-path models compute in FP64 also when precision is HDMR_MIXED.
- * paths (host, count entries, may be NULL) receives the path used per model:
- * -1 none (n = 0), 0 persistent gather, 1 cell-sorted, 2 cell-sorted with the
- * smaller row batch.  All models must live on one device (max d 1900).  The
+ * data on each candidate path (persistent gather in plain precision, and the
+ * cell-sorted path with five contraction tile shapes: row batch, work-item
+ * size, grid) and the fastest is kept per (model, size bucket floor(log2 n),
+ * precision) -- the call that measures leaves correct values.  With
+ * HDMR_MIXED every model with grid points takes the cell-sorted path (the
+ * gather kernel is FP64 only).  paths (host, count entries, may be NULL)
+ * receives the path used per model: -1 none (n = 0), 0 persistent gather,
+ * 1 + v the cell-sorted path with tile shape v (bit 0: the smaller row batch,
+ * bit 1: work items of 128 points instead of 256, bit 2: a persistent grid of
+ * three workgroups per CU).  All models must live on one device (max d 1900).  The
  * caller must not free or overwrite a model while a batched call using it
  * may still run on a stream.  The cached graphs are released when their
  * models are freed. */

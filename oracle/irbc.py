@@ -70,3 +70,46 @@ def residuals(policy, p, X, choice):
     cons = (lam[:, None] / tau[None, :]) ** (-gam[None, :])
     R[:, N] = (a * A * k ** p["alpha"] + k * ((1.0 - p["delta"]) - 0.5 * p["phi"] * g1 ** 2) - k1 - cons).sum(axis=1)
     return R, E
+
+
+def solve(policy, p, X, x0, max_iter=30, tol=1e-11, rel=1e-7):
+    """Newton on the first-order conditions per state: forward-difference
+    Jacobian (unknown i raised by rel max(1, |x_i|)), the linear systems solved
+    by numpy.linalg.solve, states whose largest |residual| is <= tol left as
+    they are.  Returns (x, updates made, largest |residual| at exit)."""
+    x = np.array(x0, dtype=np.float64, copy=True)
+    n, M = x.shape
+    it = 0
+    while True:
+        R, _ = residuals(policy, p, X, x)
+        worst = np.abs(R).max(axis=1)
+        if np.all(worst <= tol) or it >= max_iter:
+            return x, it, float(worst.max())
+        J = np.empty((n, M, M))
+        for i in range(M):
+            h = rel * np.maximum(1.0, np.abs(x[:, i]))
+            xp = x.copy()
+            xp[:, i] += h
+            Ri, _ = residuals(policy, p, X, xp)
+            J[:, :, i] = (Ri - R) / h[:, None]
+        dx = np.linalg.solve(J, -R[:, :, None])[:, :, 0]
+        act = worst > tol
+        x[act] += dx[act]
+        it += 1
+
+
+def euler_errors(policy, p, X):
+    """Unit-free Euler-equation errors of a policy (its own choice at X, the
+    same policy next period): |R_j| / |lambda (1 + phi g_j)| per country and
+    |R_N| / sum_j c_j for the resource constraint."""
+    N = p["N"]
+    C = evaluate(policy, X)
+    R, _ = residuals(policy, p, X, C)
+    A, gam, tau = constants(p)
+    k = p["k_lo"] + np.asarray(X)[:, N:] * (p["k_hi"] - p["k_lo"])
+    g1 = C[:, :N] / k - 1.0
+    lam = C[:, N]
+    err = np.empty_like(R)
+    err[:, :N] = np.abs(R[:, :N]) / np.abs(lam[:, None] * (1.0 + p["phi"] * g1))
+    err[:, N] = np.abs(R[:, N]) / ((lam[:, None] / tau[None, :]) ** (-gam[None, :])).sum(axis=1)
+    return err

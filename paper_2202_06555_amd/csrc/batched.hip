@@ -7,8 +7,11 @@
 //     queue counter until the queue is empty;
 //   * an autotuner measures, per (model, size bucket of n, precision), the
 //     candidate paths on the call's own data -- the persistent gather kernel
-//     and the cell-sorted path with its two row-batch shapes -- and keeps the
-//     fastest for later calls;
+//     (plain precision) and the cell-sorted path with five contraction tile
+//     shapes (row batch, work-item size, grid) -- and keeps the fastest for
+//     later calls;
+//   * mixed-precision models always take the cell-sorted path (the gather
+//     kernel computes in FP64 only);
 //   * the persistent launch (queue reset + kernel) is captured once per batch
 //     signature into a hipGraph on a private stream and replayed afterwards;
 //     models on the cell-sorted path run after it on the caller's stream.
@@ -167,7 +170,10 @@ __global__ __launch_bounds__(256) void k_eval_batched(const BatchItem *__restric
 
 // ---- host side ------------------------------------------------------------
 
-enum PathChoice : int32_t { PATH_NONE = -1, PATH_GATHER = 0, PATH_SORTED = 1, PATH_SORTED_ALT = 2 };
+// Path codes: the gather kernel, or the cell-sorted path with tile shape
+// (variant of eval_sorted) code - 1.
+enum PathChoice : int32_t { PATH_NONE = -1, PATH_GATHER = 0, PATH_SORTED = 1 };
+constexpr int32_t SORTED_SHAPES[] = {0, 1, 2, 4, 6};  // eval_sorted variants the tuner measures
 
 constexpr int64_t TUNE_MIN_POINTS = 16384;  // below this the gather kernel is used untuned
 constexpr size_t GRAPH_CACHE_MAX = 32;
@@ -276,22 +282,24 @@ int gather_single(const hdmr_model *mdl, const double *X, double *Y, int64_t n, 
 int run_path(int32_t path, const hdmr_model *mdl, const double *X, double *Y, int64_t n, int precision,
              hipStream_t s) {
   if (path == PATH_GATHER) return gather_single(mdl, X, Y, n, s);
-  return eval_sorted(mdl, X, n, Y, precision, s, path == PATH_SORTED_ALT ? 1 : 0);
+  return eval_sorted(mdl, X, n, Y, precision, s, path - PATH_SORTED);
 }
 
 // Measure the candidates on the call's data; the last one run leaves its
 // (correct) values in Y.  Returns the fastest.
 int autotune(const hdmr_model *mdl, const double *X, double *Y, int64_t n, int precision, hipStream_t s,
              int32_t *best) {
-  const int32_t cands[3] = {PATH_GATHER, PATH_SORTED, PATH_SORTED_ALT};
+  std::vector<int32_t> cands;
+  if (precision == HDMR_PLAIN_FP64) cands.push_back(PATH_GATHER);
+  if (!mdl->passes.empty())
+    for (int32_t v : SORTED_SHAPES) cands.push_back(PATH_SORTED + v);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HDMR_HIP(hipEventCreate(&e0));
   HDMR_HIP(hipEventCreate(&e1));
   float best_ms = 0.f;
-  *best = PATH_SORTED;
+  *best = cands.empty() ? PATH_GATHER : cands[0];
   int rc = HDMR_OK;
-  for (int c = 0; c < 3 && !rc; ++c) {
-    if (cands[c] != PATH_GATHER && mdl->passes.empty()) continue;
+  for (size_t c = 0; c < cands.size() && !rc; ++c) {
     hipError_t e = hipEventRecord(e0, s);
     if (e == hipSuccess) rc = run_path(cands[c], mdl, X, Y, n, precision, s);
     if (!rc && e == hipSuccess) e = hipEventRecord(e1, s);
@@ -365,8 +373,12 @@ extern "C" int hdmr_eval_batched(const hdmr_model *const *models, const double *
       done[i] = 1;
       continue;
     }
-    if (n[i] < TUNE_MIN_POINTS || models[i]->passes.empty()) {
-      choice[i] = PATH_GATHER;
+    if (models[i]->passes.empty() || (n[i] < TUNE_MIN_POINTS && precision == HDMR_PLAIN_FP64)) {
+      choice[i] = PATH_GATHER;  // models without grid points: c0 only, exact in any precision
+      continue;
+    }
+    if (n[i] < TUNE_MIN_POINTS) {
+      choice[i] = PATH_SORTED;  // mixed precision: the cell-sorted path, default tile shape
       continue;
     }
     const TuneKey key{models[i], bucket_of(n[i]), precision};

@@ -66,6 +66,7 @@ constexpr int TR_FP64_ALT = 32;          // the alternative row batches an autot
 constexpr int TR_MIXED_ALT = 32;
 constexpr int TILE_GRID = HDMR_TILE_GRID;  // most workgroups of a contraction launch
 constexpr int CHUNK = HDMR_CHUNK;          // points per work item (<= 4 sub-tiles)
+constexpr int CHUNK_MIN = 64;              // smallest work item a tile shape may ask for
 
 __global__ void k_transpose(const double *__restrict__ X, int64_t n, int d, double *__restrict__ XT,
                             uint8_t *__restrict__ nanflag) {
@@ -144,22 +145,22 @@ __global__ void k_bounds(const uint16_t *__restrict__ ks, int64_t n, uint32_t *_
 }
 
 __global__ void k_tile_counts(const uint32_t *__restrict__ start, const uint32_t *__restrict__ end, int nbins,
-                              uint32_t *__restrict__ ntile) {
+                              uint32_t chunk, uint32_t *__restrict__ ntile) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < nbins) ntile[b] = (end[b] - start[b] + CHUNK - 1) / CHUNK;
+  if (b < nbins) ntile[b] = (end[b] - start[b] + chunk - 1) / chunk;
 }
 
-// Work items of <= CHUNK consecutive sorted points of one cell: (first sorted
-// point, count, rows of the cell, first CSR entry of the cell).
+// Work items of <= chunk (<= CHUNK) consecutive sorted points of one cell:
+// (first sorted point, count, rows of the cell, first CSR entry of the cell).
 __global__ void k_write_tiles(const uint32_t *__restrict__ start, const uint32_t *__restrict__ end,
                               const uint32_t *__restrict__ ntile, const uint32_t *__restrict__ toff,
                               const uint32_t *__restrict__ crows, const uint32_t *__restrict__ coff, int nbins,
-                              uint4 *__restrict__ tiles, uint32_t *__restrict__ ntiles) {
+                              uint32_t chunk, uint4 *__restrict__ tiles, uint32_t *__restrict__ ntiles) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nbins) return;
   const uint32_t s0 = start[b], cnt = end[b] - start[b];
   for (uint32_t t = 0; t < ntile[b]; ++t)
-    tiles[toff[b] + t] = make_uint4(s0 + t * CHUNK, min(cnt - t * CHUNK, (uint32_t)CHUNK), crows[b], coff[b]);
+    tiles[toff[b] + t] = make_uint4(s0 + t * chunk, min(cnt - t * chunk, chunk), crows[b], coff[b]);
   if (b == nbins - 1) *ntiles = toff[b] + ntile[b];
 }
 
@@ -980,7 +981,7 @@ struct Workspace {
 };
 
 void carve_workspace(Carve &C, Workspace &W, int64_t n, int d, int AS, bool mixed, int64_t list_max, size_t tmp_bytes) {
-  const size_t max_tiles = (size_t)(n / CHUNK) + 65536 + 1;
+  const size_t max_tiles = (size_t)(n / CHUNK_MIN) + 65536 + 1;
   W.xt = C.take<double>((size_t)n * d);
   W.acc = C.take<double>((size_t)n * AS);
   W.acc32 = mixed ? C.take<float>((size_t)n * AS) : nullptr;
@@ -1141,7 +1142,15 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
   // contraction workgroups: about one per work item (items hold <= CHUNK
   // points of one cell), within [1024, TILE_GRID]; each walks the items
   // with a stride of the grid
-  const unsigned tgrid = (unsigned)std::max<int64_t>(1024, std::min<int64_t>((n + CHUNK - 1) / CHUNK, TILE_GRID));
+  // tile shape (variant bits): 1 = the smaller row batch, 2 = work items of
+  // CHUNK / 2 points, 4 = a persistent grid of 3 workgroups per CU
+  const uint32_t chunk = (variant & 2) ? CHUNK / 2 : CHUNK;
+  unsigned tgrid = (unsigned)std::max<int64_t>(1024, std::min<int64_t>((n + chunk - 1) / chunk, TILE_GRID));
+  if (variant & 4) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, model->device) == hipSuccess && cus > 0)
+      tgrid = (unsigned)(3 * cus);
+  }
   const unsigned ga = (unsigned)std::min<int64_t>((n * AS + 255) / 256, 65536);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_fill_u8, dim3(gs), dim3(256), 0, stream, W.nanflag, n);
@@ -1184,12 +1193,12 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
       if (e != hipSuccess) break;
       hipLaunchKernelGGL(k_cell_rows, dim3(gc), dim3(256), 0, side, M, P, model->pass_tups, B.bstart, B.bend, nbins,
                          (const uint32_t *)B.coff, B.clist, B.cidx, B.crows);
-      hipLaunchKernelGGL(k_tile_counts, dim3(gb), dim3(256), 0, side, B.bstart, B.bend, nbins, B.ntile);
+      hipLaunchKernelGGL(k_tile_counts, dim3(gb), dim3(256), 0, side, B.bstart, B.bend, nbins, chunk, B.ntile);
       tb = tmp_bytes;
       e = hipcub::DeviceScan::ExclusiveSum(B.tmp, tb, B.ntile, B.toff, nbins, side);
       if (e != hipSuccess) break;
       hipLaunchKernelGGL(k_write_tiles, dim3(gb), dim3(256), 0, side, B.bstart, B.bend, B.ntile, B.toff, B.crows,
-                         B.coff, nbins, B.tiles, B.ntiles);
+                         B.coff, nbins, chunk, B.tiles, B.ntiles);
     }
     if ((e = hipEventRecord(ev_sorted[bsel], side)) != hipSuccess) break;
     if ((e = hipStreamWaitEvent(stream, ev_sorted[bsel], 0)) != hipSuccess) break;
@@ -1203,10 +1212,10 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
         else if (G)
           hipLaunchKernelGGL((k_tile_fp64<TR_GRAD, true, false>), dim3(tgrid), dim3(256), 0, stream, M, P, B.tiles,
                              B.ntiles, B.clist, B.cidx, B.spid, B.xk, n, W.acc, AS, o0, G);
-        else if (!mixed && variant == 0 && narrow)
+        else if (!mixed && !(variant & 1) && narrow)
           hipLaunchKernelGGL((k_tile_fp64<TR_FP64, false, true>), dim3(tgrid), dim3(256), 0, stream, M, P, B.tiles,
                              B.ntiles, B.clist, B.cidx, B.spid, B.xk, n, W.acc, AS, o0, (double *)nullptr);
-        else if (!mixed && variant == 0)
+        else if (!mixed && !(variant & 1))
           hipLaunchKernelGGL((k_tile_fp64<TR_FP64, false, false>), dim3(tgrid), dim3(256), 0, stream, M, P, B.tiles,
                              B.ntiles, B.clist, B.cidx, B.spid, B.xk, n, W.acc, AS, o0, (double *)nullptr);
         else if (!mixed && narrow)
@@ -1218,7 +1227,7 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
         else if (split2)
           hipLaunchKernelGGL((k_tile_mixed<TR_MIXED, 2>), dim3(tgrid), dim3(256), 0, stream, M, P, B.tiles, B.ntiles,
                              B.clist, B.cidx, B.spid, B.xk, (const float *)model->alpha32, n, W.acc32, AS, o0);
-        else if (variant == 0)
+        else if (!(variant & 1))
           hipLaunchKernelGGL((k_tile_mixed<TR_MIXED, 3>), dim3(tgrid), dim3(256), 0, stream, M, P, B.tiles, B.ntiles,
                              B.clist, B.cidx, B.spid, B.xk, (const float *)model->alpha32, n, W.acc32, AS, o0);
         else

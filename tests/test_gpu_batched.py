@@ -69,7 +69,8 @@ def test_batched_matches_oracle(hd):
     gms = [hd.hdmr_model_from_surpluses(mo) for mo in models]
     Y, paths = hd.hdmr_eval_batched(gms, [_dev(P) for P in X])
     print("paths", paths.tolist())
-    assert paths[4] == -1 and all(p in (0, 1, 2) for i, p in enumerate(paths) if i != 4)
+    # -1 none, 0 gather, 1 + v cell-sorted with tile shape v in {0, 1, 2, 4, 6}
+    assert paths[4] == -1 and all(p in (0, 1, 2, 3, 5, 7) for i, p in enumerate(paths) if i != 4)
     assert paths[1] == 0 and paths[0] == 0
     _check_against_oracle(models, X, Y)
 
@@ -97,16 +98,20 @@ def test_graph_replay_with_new_data(hd):
 
 
 def test_batched_mixed_precision(hd):
+    # every model with grid points takes the mixed-capable cell-sorted path
+    # (the FP64 gather kernel is never used for HDMR_MIXED); per-output bar
     models, X = _batch(seed=2)
     gms = [hd.hdmr_model_from_surpluses(mo) for mo in models]
     Y, paths = hd.hdmr_eval_batched(gms, [_dev(P) for P in X], precision=hd.MIXED)
-    for mo, P, V in zip(models, X, Y):
+    for mo, P, V, path in zip(models, X, Y, paths):
         if P.shape[0] == 0:
             continue
+        assert path >= 1, path
         ok = ~np.isnan(P).any(axis=1)
         ref = oracle.evaluate(mo, P[ok][:2000])
         got = V.cpu().numpy()[ok][:2000]
-        assert np.linalg.norm(got - ref) <= 1e-6 * np.linalg.norm(ref)
+        rel = (np.abs(got - ref).max(axis=0) / np.abs(ref).max(axis=0)).max()
+        assert rel <= 1e-6, rel
 
 
 def test_empty_and_single(hd):
@@ -117,3 +122,37 @@ def test_empty_and_single(hd):
     assert paths.tolist() == [-1] and Y[0].shape == (0, 2)
     Y, paths = hd.hdmr_eval_batched([], [])
     assert Y == [] and len(paths) == 0
+
+
+@pytest.mark.parametrize("precision", ["plain", "mixed"])
+def test_c4_shaped_batch_sampled(hd, precision):
+    # four models of the batched workload's generator (d = 22, 13, 10, 53; all
+    # one- and two-dimensional components; random downward-closed grids of
+    # log-uniform size 50..20000; m = d/2 + 1), 1e4..4e4 points each, one
+    # batched call (autotuned paths), 300 sampled points per model against
+    # the oracle: plain max-abs 1e-12, mixed per output 1e-6
+    import torch
+    prec = hd.PLAIN_FP64 if precision == "plain" else hd.MIXED
+    models, X = [], []
+    for i in (11, 23, 27, 1):
+        mo, P = ws.c4_model(i, seed=0, n_range=(10_000, 40_000))
+        models.append(mo)
+        X.append(P)
+    gms = [hd.hdmr_model_from_surpluses(mo) for mo in models]
+    Xd = [_dev(P) for P in X]
+    Y, paths = hd.hdmr_eval_batched(gms, Xd, precision=prec)        # tuning call
+    Y, paths2 = hd.hdmr_eval_batched(gms, Xd, precision=prec)       # tuned call
+    torch.cuda.synchronize()
+    print("c4-shaped batch (%s): d %s, rows %s, n %s, paths %s" %
+          (precision, [mo["d"] for mo in models], [sum(l.shape[0] for l in mo["levels"]) for mo in models],
+           [P.shape[0] for P in X], paths2.tolist()))
+    assert paths.tolist() == paths2.tolist()
+    for mo, P, V in zip(models, X, Y):
+        idx = np.random.default_rng(mo["d"]).choice(P.shape[0], 300, replace=False)
+        ref = oracle.evaluate(mo, P[idx])
+        got = V.cpu().numpy()[idx]
+        if precision == "plain":
+            assert np.abs(got - ref).max() <= TOL
+        else:
+            rel = (np.abs(got - ref).max(axis=0) / np.abs(ref).max(axis=0)).max()
+            assert rel <= 1e-6, rel

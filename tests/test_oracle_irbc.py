@@ -70,3 +70,20 @@ def test_constant_policy_expectation_closed_form():
     a = p["a_lo"] + X[:, :N] * (p["a_hi"] - p["a_lo"])
     ref = L * (A * p["alpha"] * a ** p["rho"] * S + 1.0 - p["delta"])
     np.testing.assert_allclose(E, ref, rtol=1e-14)
+
+
+def test_newton_converges_to_the_deterministic_steady_state():
+    # from a perturbed start the solve reaches the closed-form steady state
+    # (k' = 1, lambda = ((A - delta) / A)^(-1/gamma)) of the deterministic model
+    N = 3
+    p = ws.irbc_params(N, sigma=0.0, gamma_span=0.0)
+    A, gam, _ = irbc.constants(p)
+    lam = ((A - p["delta"]) / A) ** (-1.0 / gam[0])
+    policy = _constant_policy(N, 1.0, lam)
+    X = np.full((3, 2 * N), 0.5)
+    x0 = np.tile(np.concatenate([np.ones(N), [lam]]), (3, 1)) * np.array([[1.01], [0.98], [1.003]])
+    x, it, worst = irbc.solve(policy, p, X, x0, tol=1e-12)
+    assert worst <= 1e-12 and 1 <= it <= 10
+    np.testing.assert_allclose(x, np.tile(np.concatenate([np.ones(N), [lam]]), (3, 1)), rtol=1e-10)
+    # the steady-state policy has zero Euler errors there
+    np.testing.assert_allclose(irbc.euler_errors(policy, p, X), 0.0, atol=1e-14)

@@ -38,14 +38,45 @@ def test_named_configurations():
     assert len(c5["comps"]) == 600 and c5["m"] == 151
 
 
-def test_batched_models_shapes():
-    models, points = ws.batched_models(count=3, seed=0)
-    again, _ = ws.batched_models(count=3, seed=0)
-    for mo, P, mo2 in zip(models, points, again):
+def _closed(lv, ix):
+    pts = {(tuple(l), tuple(i)) for l, i in zip(lv.tolist(), ix.tolist())}
+    for l, i in pts:
+        for q in range(len(l)):
+            if l[q] > 1:
+                pl, pi = list(l), list(i)
+                pl[q] -= 1
+                a, b = (i[q] - 1) // 2, (i[q] + 1) // 2
+                pi[q] = a if a % 2 else b
+                if (tuple(pl), tuple(pi)) not in pts:
+                    return False
+    return len(pts) == lv.shape[0]
+
+
+def test_closed_grids():
+    # random downward-closed grids: at least the target size, every parent
+    # present, odd indices inside their level, deterministic per seed
+    for k, target in [(1, 1), (1, 300), (2, 50), (2, 4000)]:
+        lv, ix = ws.closed_grid(k, target, seed=target + k)
+        assert lv.shape == (target, k) and _closed(lv, ix)
+        assert np.all(ix % 2 == 1) and np.all(ix < (1 << lv.astype(np.int64)))
+        assert tuple(lv[0]) == (1,) * k and tuple(ix[0]) == (1,) * k
+        lv2, ix2 = ws.closed_grid(k, target, seed=target + k)
+        assert np.array_equal(lv, lv2) and np.array_equal(ix, ix2)
+    # a 1-D grid capped at level 3 holds at most 7 points
+    lv, ix = ws.closed_grid(1, 100, seed=1, lcap=3)
+    assert lv.shape[0] == 7 and _closed(lv, ix)
+
+
+def test_batched_workload_shapes():
+    # the generator of the 64-model batched workload, d capped for speed here
+    for i in (23, 27):
+        mo, P = ws.c4_model(i, seed=0, n_range=(10_000, 20_000))
+        mo2, P2 = ws.c4_model(i, seed=0, n_range=(10_000, 20_000))
         d, m = mo["d"], mo["m"]
-        assert 10 <= d <= 30 and m == d // 2 + 1
+        assert 10 <= d <= 100 and m == d // 2 + 1
         assert len(mo["comps"]) == d + d * (d - 1) // 2
-        assert 10_000 <= P.shape[0] <= 100_000 and P.shape[1] == d
+        assert 10_000 <= P.shape[0] <= 20_000 and P.shape[1] == d
         for lv, ix, al in zip(mo["levels"], mo["indices"], mo["alpha"]):
-            assert lv.shape == ix.shape and al.shape == (lv.shape[0], m)
-        assert all(np.array_equal(a, b) for a, b in zip(mo["alpha"], mo2["alpha"]))
+            assert 50 <= lv.shape[0] <= 20_000 and lv.shape == ix.shape and al.shape == (lv.shape[0], m)
+        assert _closed(mo["levels"][-1], mo["indices"][-1])
+        assert all(np.array_equal(a, b) for a, b in zip(mo["alpha"], mo2["alpha"])) and np.array_equal(P, P2)

@@ -35,10 +35,10 @@ _LIB = None
 
 def build_testfn(force: bool = True) -> str:
     """Compile the C test function with gcc (OpenMP) into workloads/libtestfn.so."""
-    src = os.path.join(_HERE, "testfn.c")
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+    srcs = [os.path.join(_HERE, "testfn.c"), os.path.join(_HERE, "gridgen.c")]
+    if force or not os.path.exists(_SO) or any(os.path.getmtime(_SO) < os.path.getmtime(s) for s in srcs):
         tmp = _SO + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-o", tmp, src, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-o", tmp] + srcs + ["-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -54,6 +54,9 @@ def _lib():
             lib.tf_prepare.argtypes = [ctypes.c_void_p]
             lib.tf_release.restype = None
             lib.tf_release.argtypes = [ctypes.c_void_p]
+            lib.gg_closed_grid.restype = ctypes.c_int64
+            lib.gg_closed_grid.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
             for nm in ("tf_eval", "tf_eval_direct"):
                 fn = getattr(lib, nm)
                 fn.restype = ctypes.c_int
@@ -274,42 +277,6 @@ def regular_grid_size(k, ell):
     return _regular_cached(k, ell)[0].shape[0]
 
 
-def batched_models(count=64, seed=0, d_range=(10, 30), size_range=(50, 5000), n_range=(10_000, 100_000),
-                   max_ell=10):
-    """A batch of independent order-2 models of uneven shape (the batched
-    workload).  Model i draws from default_rng(seed + i): d ~ U{d_range},
-    m = d // 2 + 1, c0 ~ N(0,1)^m, then per component (all d one-dimensional
-    and all C(d,2) two-dimensional index sets, in (|S|, lexicographic) order) a
-    target size N ~ logU(size_range) realised as the smallest regular
-    (downward-closed) sparse grid with at least N points (level <= max_ell),
-    with alpha ~ N(0,1) 2^(-2|l|_1) per grid point; then n ~ logU(n_range)
-    evaluation points uniform on [0,1]^d.  Returns (models, points)."""
-    models, points = [], []
-    for i in range(count):
-        rng = np.random.default_rng(seed + i)
-        d = int(rng.integers(d_range[0], d_range[1] + 1))
-        m = d // 2 + 1
-        c0 = rng.standard_normal(m)
-        comps = all_components(d, 2)
-        levels, indices, alpha = [], [], []
-        for S in comps:
-            k = len(S)
-            target = float(np.exp(rng.uniform(np.log(size_range[0]), np.log(size_range[1]))))
-            ell = 1
-            while ell < max_ell and regular_grid_size(k, ell) < target:
-                ell += 1
-            lv, ix = _regular_cached(k, ell)
-            z = rng.standard_normal((lv.shape[0], m))
-            levels.append(lv)
-            indices.append(ix)
-            alpha.append(z * np.ldexp(1.0, -2 * lv.astype(np.int64).sum(axis=1))[:, None])
-        n = int(np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1]))))
-        models.append({"d": d, "m": m, "c0": c0, "comps": comps, "weights": np.ones(len(comps)),
-                       "levels": levels, "indices": indices, "alpha": alpha})
-        points.append(rng.random((n, d)))
-    return models, points
-
-
 # --------------------------------------------------------------------------
 # named workload configurations
 # --------------------------------------------------------------------------
@@ -407,3 +374,52 @@ def irbc_states(n, N, seed):
     X = rng.random((n, 2 * N))
     C = IrbcGuess(N)(X) * (1.0 + 0.02 * rng.uniform(-1.0, 1.0, size=(n, N + 1)))
     return X, C
+
+
+# --------------------------------------------------------------------------
+# batched workload at its stated shape
+# --------------------------------------------------------------------------
+
+def closed_grid(k, target, seed, lcap=16):
+    """A random downward-closed grid of a k-dimensional component with at
+    least ``target`` points (gridgen.c): (levels (n x k) uint8, indices
+    (n x k) uint32) in the order the points were added."""
+    cap = int(target)
+    lv = np.zeros((cap, k), np.uint8)
+    ix = np.zeros((cap, k), np.uint32)
+    n = _lib().gg_closed_grid(int(k), int(target), int(lcap), int(seed) & ((1 << 64) - 1), lv.ctypes.data,
+                              ix.ctypes.data, cap)
+    if n < 0:
+        raise RuntimeError("grid generation failed")
+    return lv[:n].copy(), ix[:n].copy()
+
+
+def c4_model(i, seed=0, d_range=(10, 100), size_range=(50, 20000), n_range=(10_000, 1_000_000), max_d=None):
+    """Model i of the batched workload: draws from default_rng(seed + i)
+    d ~ U{d_range} (capped at max_d if given), m = d // 2 + 1, c0 ~ N(0,1)^m;
+    then per component (all d one-dimensional and all C(d,2) two-dimensional
+    index sets, in (|S|, lexicographic) order) a target size
+    N ~ logU(size_range), a random downward-closed grid of at least N points
+    (closed_grid with a seed drawn from the same generator, levels <= 16) and
+    alpha ~ N(0,1) 2^(-2|l|_1) per grid point; then n ~ logU(n_range) points
+    uniform on [0,1]^d.  Returns (model, points)."""
+    rng = np.random.default_rng(seed + i)
+    d = int(rng.integers(d_range[0], d_range[1] + 1))
+    if max_d is not None:
+        d = min(d, int(max_d))
+    m = d // 2 + 1
+    c0 = rng.standard_normal(m)
+    comps = all_components(d, 2)
+    levels, indices, alpha = [], [], []
+    for S in comps:
+        k = len(S)
+        target = int(np.ceil(np.exp(rng.uniform(np.log(size_range[0]), np.log(size_range[1])))))
+        lv, ix = closed_grid(k, target, int(rng.integers(0, 2 ** 63)))
+        z = rng.standard_normal((lv.shape[0], m))
+        levels.append(lv)
+        indices.append(ix)
+        alpha.append(z * np.ldexp(1.0, -2 * lv.astype(np.int64).sum(axis=1))[:, None])
+    n = int(np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1]))))
+    model = {"d": d, "m": m, "c0": c0, "comps": comps, "weights": np.ones(len(comps)),
+             "levels": levels, "indices": indices, "alpha": alpha}
+    return model, rng.random((n, d))
