@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--train-points", type=int, default=2_000_000, help="surrogate: interpolant training pairs")
     ap.add_argument("--epochs", type=int, default=3, help="surrogate: passes over the training pairs")
     ap.add_argument("--serve-points", type=int, default=2_000_000, help="surrogate: points served")
+    ap.add_argument("--train-seconds", type=float, default=0.0,
+                    help="surrogate: train in one-epoch segments for this long (0: --epochs in one run)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the evaluation shards by points with no exchange, "
@@ -378,6 +380,7 @@ def bench_batched(args):
     gms, X, Y, meta = [], [], [], []
     for i in range(count):
         mo, P = futs.pop(i).result()
+        log("model %d generated (d=%d) at %.1f s" % (i, mo["d"], time.time() - t0))
         if nxt < count:
             futs[nxt] = ex.submit(_gen_c4, nxt)
             nxt += 1
@@ -394,12 +397,23 @@ def bench_batched(args):
     dev_gb = sum(hd.hdmr_get_info(g)["device_bytes"] for g in gms) / 1e9
     log("batched: %d models, %d rows, %d points, %.1f GB of models on the device, set up in %.1f s" %
         (len(gms), rows, npts, dev_gb, setup_s))
-    hits = sum(hd.hdmr_eval_stats(g, x)[0] * mm["m"] for g, x, mm in zip(gms, X, meta))
+    hits = 0
+    for i, (g, x, mm) in enumerate(zip(gms, X, meta)):
+        hits += hd.hdmr_eval_stats(g, x)[0] * mm["m"]
+        if i % 8 == 7:
+            log("work counted for %d models" % (i + 1))
+    # path and tile-shape measurement, model by model (the choices persist
+    # per model and size bucket; the batched calls below reuse them)
     t0 = time.time()
-    _, paths = hd.hdmr_eval_batched(gms, X, Y)          # first call: path and tile-shape measurement
+    for i in range(len(gms)):
+        hd.hdmr_eval_batched([gms[i]], [X[i]], [Y[i]])
+        torch.cuda.synchronize()
+        log("tuned model %d (d=%d, %d rows, n=%d) at %.1f s" % (i, meta[i]["d"], meta[i]["rows"], meta[i]["n"],
+                                                                time.time() - t0))
+    _, paths = hd.hdmr_eval_batched(gms, X, Y)
     torch.cuda.synchronize()
     tune_s = time.time() - t0
-    log("tuning call %.1f s; paths %s" % (tune_s, paths.tolist()))
+    log("tuning %.1f s; paths %s" % (tune_s, paths.tolist()))
     t = _timed(lambda: hd.hdmr_eval_batched(gms, X, Y), args.steps, args.warmup)
     units = sum(mm["n"] * mm["m"] for mm in meta)
     flops = 2.0 * hits
@@ -624,13 +638,37 @@ def bench_surrogate(args):
     rng = np.random.default_rng(5)
     order = np.concatenate([rng.permutation(ntr) for _ in range(args.epochs + 1)])[:steps * B]
     order = torch.from_numpy(order.astype(np.int64)).to("cuda:0")
+    Xv = torch.from_numpy(ws.points_for(cfg, n=100_000, seed=3)).to("cuda:0")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    losses = sg.mlp_train(net, Xtr, Ytr, order, steps=steps, batch=B, lr0=1e-3)
+    curve = []
+    if args.train_seconds > 0:
+        # training to a measured plateau: segments of one epoch, each a cosine
+        # decay from a learning rate that shrinks by 0.7 per segment; after
+        # every segment the per-output max-abs error on the validation points
+        seg = max(1, ntr // B)
+        lr, k, all_losses = 1e-3, 0, []
+        while time.perf_counter() - t0 < args.train_seconds:
+            o = np.concatenate([rng.permutation(ntr) for _ in range(seg * B // ntr + 1)])[:seg * B]
+            o = torch.from_numpy(o.astype(np.int64)).to("cuda:0")
+            all_losses.append(sg.mlp_train(net, Xtr, Ytr, o, steps=seg, batch=B, lr0=lr))
+            probe = sg.mlp_route_create(net, full, Xv, 1e-4)
+            kk, e, _ = sg.mlp_route_info(probe)
+            k += 1
+            curve.append({"segment": k, "steps": k * seg, "seconds": time.perf_counter() - t0,
+                          "loss": float(all_losses[-1][-min(200, seg):].mean()), "lr0": lr,
+                          "val_max_err_max": float(e.max()), "val_max_err_median": float(np.median(e)),
+                          "val_max_err_min": float(e.min()), "outputs_at_1e-4": int(kk)})
+            log("segment %d: %d steps, %.1f s, loss %.4f, validated max-abs error min %.2e median %.2e max %.2e"
+                % (k, k * seg, curve[-1]["seconds"], curve[-1]["loss"], e.min(), np.median(e), e.max()))
+            lr *= 0.7
+        losses = np.concatenate(all_losses)
+        steps = k * seg
+    else:
+        losses = sg.mlp_train(net, Xtr, Ytr, order, steps=steps, batch=B, lr0=1e-3)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     del Xtr, Ytr, order
-    Xv = torch.from_numpy(ws.points_for(cfg, n=100_000, seed=3)).to("cuda:0")
     route = sg.mlp_route_create(net, full, Xv, 1e-4)
     k, err, use = sg.mlp_route_info(route)
     Xs = torch.from_numpy(ws.points_for(cfg, n=args.serve_points, seed=2)).to("cuda:0")
@@ -649,7 +687,8 @@ def bench_surrogate(args):
                                "pairs (%d epochs, batch 4096); %d served points" % (ntr, args.epochs, ns),
                    "outputs_on_network": int(k), "validated_max_abs_err": {"min": float(err.min()),
                    "median": float(np.median(err)), "max": float(err.max())},
-                   "train_s": t_train, "loss_first": float(losses[:50].mean()), "loss_last": float(losses[-50:].mean()),
+                   "train_s": t_train, "train_steps": int(steps), "training_curve": curve,
+                   "loss_first": float(losses[:50].mean()), "loss_last": float(losses[-50:].mean()),
                    "network_only_evals_per_s": ns * m / t_mlp, "interpolant_evals_per_s": ns * m / t_int},
         "roofline": {"bound": "mfma", "achieved": flops_fwd / t_mlp / 1e12, "peak": BF16_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": flops_fwd / t_mlp / BF16_PEAK, "traffic": None,

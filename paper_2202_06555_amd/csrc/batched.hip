@@ -299,7 +299,11 @@ int autotune(const hdmr_model *mdl, const double *X, double *Y, int64_t n, int p
   float best_ms = 0.f;
   *best = cands.empty() ? PATH_GATHER : cands[0];
   int rc = HDMR_OK;
+  float gather_ms = -1.f, sorted0_ms = -1.f;
   for (size_t c = 0; c < cands.size() && !rc; ++c) {
+    // the other tile shapes are measured only while the cell-sorted path is
+    // within 2x of the gather kernel (a path that far behind is not tuned)
+    if (cands[c] > PATH_SORTED && gather_ms >= 0.f && sorted0_ms > 2.f * gather_ms) break;
     hipError_t e = hipEventRecord(e0, s);
     if (e == hipSuccess) rc = run_path(cands[c], mdl, X, Y, n, precision, s);
     if (!rc && e == hipSuccess) e = hipEventRecord(e1, s);
@@ -307,6 +311,8 @@ int autotune(const hdmr_model *mdl, const double *X, double *Y, int64_t n, int p
     float ms = 0.f;
     if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
     if (!rc && e != hipSuccess) rc = hip_fail(e, "autotune");
+    if (!rc && cands[c] == PATH_GATHER) gather_ms = ms;
+    if (!rc && cands[c] == PATH_SORTED) sorted0_ms = ms;
     if (!rc && (c == 0 || ms < best_ms)) {
       best_ms = ms;
       *best = cands[c];

@@ -283,3 +283,94 @@ def test_surrogate_gain_over_interpolant(env):
           % (tau, res_max, fresh, t_interp * 1e3, t_routed * 1e3, t_interp / t_routed))
     assert fresh <= 1.5 * tau
     assert t_interp / t_routed >= 1.5
+
+
+# ---- the GPU network against the exact FP64 network (storage='exact') -------
+# A first-order componentwise error bound of the BF16 kernels, derived from
+# the BF16 unit roundoff u = 2^-9 (round to nearest), FP32 accumulation
+# (gamma_K = K 2^-24 for K products) and the layer widths:
+#   operands: x, the weights and every stored activation / back-propagated
+#   gradient are rounded to BF16 once (relative error <= u each);
+#   a product z = W h + b with BF16 W~, h~ (|h~ - h| <= e) has
+#     |z~ - z| <= |W| e + (2u + gamma_K) |W| |h|        (to first order);
+#   GELU: |gelu'| <= 1.13, |gelu''| <= 0.80, and the stored value adds u |h|.
+# The backward pass propagates the same terms through W^T and gelu'.  The
+# bound is computed from the exact network's magnitudes, so it holds for any
+# rounding point the kernels are allowed to have and fails for a wrong one
+# (an extra BF16 rounding of an FP32 accumulator, a dropped term).
+
+U = 2.0 ** -9
+LG1, LG2 = 1.13, 0.80
+
+
+def _fwd_bound(layers, X):
+    H = np.asarray(X, np.float64)
+    E = U * np.abs(H)
+    cache = []
+    for l, (W, b) in enumerate(layers):
+        K = W.shape[1]
+        Z = H @ W.T + b
+        EZ = E @ np.abs(W).T + (2 * U + K * 2.0 ** -24) * (np.abs(H) @ np.abs(W).T) + 2.0 ** -24 * np.abs(b)
+        cache.append((H, E, Z, EZ))
+        if l < 3:
+            Hn = omlp.gelu(Z)
+            E = LG1 * EZ + U * (np.abs(Hn) + LG1 * EZ)
+            H = Hn
+    return Z, EZ, cache
+
+
+@pytest.mark.parametrize("d,w,m,n", [(20, 64, 7, 1000), (33, 72, 19, 300), (300, 512, 151, 40000)])
+def test_forward_within_bf16_bound_of_exact_network(env, d, w, m, n):
+    hd, sg = env
+    net, p, mean, std = _net(sg, d, w, m, seed=d + 1)
+    X = np.random.default_rng(8).random((n, d))
+    Y = sg.mlp_forward(net, _dev(X)).cpu().numpy()
+    idx = np.arange(n) if n <= 2000 else np.random.default_rng(9).choice(n, 1500, replace=False)
+    layers = omlp.unpack(p, d, w, m)
+    out, _ = omlp.forward(p, X[idx], d, w, m, storage="exact")
+    ref = out * std + mean
+    _, EZ, _ = _fwd_bound(layers, X[idx])
+    bound = 1.05 * EZ * std + 2.0 ** -24 * np.abs(ref)   # first-order slack; FP32 output
+    ratio = np.abs(Y[idx] - ref) / bound
+    print("forward d=%d w=%d m=%d vs exact network: max |err| / bound = %.3f, max |err| %.2e" %
+          (d, w, m, ratio.max(), np.abs(Y[idx] - ref).max()))
+    assert ratio.max() <= 1.0
+
+
+def test_gradients_within_bf16_bound_of_exact_network(env):
+    hd, sg = env
+    import torch
+    d, w, m, B = 24, 64, 9, 512
+    net, p, mean, std = _net(sg, d, w, m, seed=15)
+    rng = np.random.default_rng(16)
+    X = rng.random((2000, d))
+    Yraw = rng.normal(size=(2000, m)) * std + mean
+    idx = rng.choice(2000, B, replace=False)
+    loss, g = sg.mlp_loss_grads(net, _dev(X), _dev(Yraw), torch.from_numpy(idx.astype(np.int64)).to("cuda:0"))
+    mu32, sd32 = sg.mlp_get_standardization(net)
+    T = (Yraw[idx] - mu32.astype(np.float64)) / sd32.astype(np.float64)
+    rl, rg = omlp.loss_and_grads(p, X[idx], T, d, w, m, storage="exact")
+    layers = omlp.unpack(p, d, w, m)
+    out, EZ, cache = _fwd_bound(layers, X[idx])
+    # backward: D = dL/dZ of a layer and its bound ED
+    D = 2.0 * (out - T) / (B * m)
+    ED = 2.0 * EZ / (B * m) + U * np.abs(D)
+    bounds = [None] * 4
+    for l in range(3, -1, -1):
+        H, E, Z, _ = cache[l]
+        W, _ = layers[l]
+        K = H.shape[0]
+        bounds[l] = (ED.T @ np.abs(H) + np.abs(D).T @ E + K * 2.0 ** -24 * (np.abs(D).T @ np.abs(H)),
+                     ED.sum(axis=0) + K * 2.0 ** -24 * np.abs(D).sum(axis=0))
+        if l > 0:
+            Zp, EZp = cache[l - 1][2], cache[l - 1][3]
+            dH = D @ W
+            EdH = ED @ np.abs(W) + (U + W.shape[0] * 2.0 ** -24) * (np.abs(D) @ np.abs(W))
+            Dn = dH * omlp.gelu_grad(Zp)
+            ED = LG1 * EdH + LG2 * np.abs(dH) * EZp + U * (np.abs(Dn) + LG1 * EdH)
+            D = Dn
+    bound = omlp.pack([(1.05 * a, 1.05 * b) for a, b in bounds])
+    ratio = np.abs(g - rg) / np.maximum(bound, 1e-300)
+    print("gradients vs exact network: max |err| / bound = %.3f" % ratio.max())
+    assert ratio.max() <= 1.0
+    assert abs(loss - rl) <= 1e-2 * rl
