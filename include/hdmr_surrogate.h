@@ -101,6 +101,18 @@ int mlp_eval_routed(const mlp_route *route, const double *X, int64_t n, double *
                     hdmr_stream_t stream);
 void mlp_route_free(mlp_route *route);
 
+/* Per-point gate of a route (the ensemble-disagreement reading of the
+ * surrogate's fallback): with a second network trained on the same data, a
+ * point whose two predictions differ by more than tau in any output the
+ * network serves takes those outputs from the interpolant `full` instead (the
+ * other outputs are routed as before).  second = NULL switches the gate off.
+ * The route borrows `second`; calls on the route must not overlap.  A gated
+ * mlp_eval_routed synchronises its stream once (the number of gated points
+ * sizes the fallback evaluation); mlp_route_gated returns that number for
+ * the last call. */
+int mlp_route_set_gate(mlp_route *route, mlp_model *second, const hdmr_model *full, double tau);
+int mlp_route_gated(const mlp_route *route, int64_t *n_gated);
+
 #ifdef __cplusplus
 }
 #endif

@@ -579,6 +579,45 @@ __global__ void k_maxerr(const double *__restrict__ A, const double *__restrict_
   if (threadIdx.x == 0) err[o] = s[0];
 }
 
+// Per-point gate: rows whose two network predictions P, P2 differ by more
+// than tau in any of the k served columns are listed in idx (order of
+// discovery; count in *cnt, which must start at 0).
+__global__ void k_gate_rows(const double *__restrict__ P, const double *__restrict__ P2, int64_t n, int m,
+                            const int32_t *__restrict__ cols, int k, double tau, int64_t *__restrict__ idx,
+                            unsigned long long *__restrict__ cnt) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    bool out = false;
+    for (int j = 0; j < k; ++j) {
+      const int c = cols[j];
+      const double dlt = fabs(P[r * m + c] - P2[r * m + c]);
+      out |= !(dlt <= tau);
+    }
+    if (out) idx[atomicAdd(cnt, 1ull)] = r;
+  }
+}
+
+__global__ void k_zero_count(unsigned long long *c) {
+  if (threadIdx.x == 0) *c = 0ull;
+}
+
+// Xg[i] = X[idx[i]] (rows of d values).
+__global__ void k_gather_rows(const double *__restrict__ X, const int64_t *__restrict__ idx, int64_t ng, int d,
+                              double *__restrict__ Xg) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ng * d; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / d;
+    Xg[e] = X[idx[i] * d + (e - i * d)];
+  }
+}
+
+// Y[idx[i]][cols[j]] = A[i][j].
+__global__ void k_scatter_rows(const double *__restrict__ A, const int64_t *__restrict__ idx, int64_t ng, int k,
+                               const int32_t *__restrict__ cols, int m, double *__restrict__ Y) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ng * k; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / k;
+    Y[idx[i] * m + cols[e - i * k]] = A[e];
+  }
+}
+
 unsigned grid_of(int64_t total) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 16384)); }
 // workgroups for one-wave-per-row kernels (4 rows per workgroup of 256)
 // K slices of the out x in weight gradient: enough 64 x 64 tiles for
@@ -773,11 +812,21 @@ struct mlp_route {
   int32_t *d_mlp_cols = nullptr, *d_fb_cols = nullptr;
   hdmr_model *order1 = nullptr;    // order-1 part restricted to the network's outputs
   hdmr_model *fallback = nullptr;  // all components restricted to the other outputs
+  // per-point gate: a second network; a point whose two predictions differ by
+  // more than gate_tau in any network-served output takes those outputs from
+  // served_full (all components, the network's outputs)
+  mlp_model *second = nullptr;
+  double gate_tau = 0.0;
+  hdmr_model *served_full = nullptr;
+  int64_t *d_gate_count = nullptr;
+  int64_t last_gated = 0;
   ~mlp_route() {
     (void)hipFree(d_mlp_cols);
     (void)hipFree(d_fb_cols);
+    (void)hipFree(d_gate_count);
     if (order1) hdmr_free(order1);
     if (fallback) hdmr_free(fallback);
+    if (served_full) hdmr_free(served_full);
   }
 };
 
@@ -1165,6 +1214,79 @@ int mlp_route_info(const mlp_route *route, int32_t *n_mlp, double *err, int32_t 
   return HDMR_OK;
 }
 
+// The per-point gate of a routed evaluation: the second network's
+// predictions at X, the rows where the two disagree by more than gate_tau in
+// a served output, and the interpolant's values of the served outputs there
+// (synchronous: the number of gated rows sizes the evaluation).
+static int gate_points(const mlp_route *route, const double *X, int64_t n, const double *P, double *Y,
+                       int32_t precision, hipStream_t s) {
+  const int32_t m = route->m, k1 = (int32_t)route->mlp_cols.size(), d = route->d;
+  double *P2 = nullptr, *Xg = nullptr, *Ag = nullptr;
+  int64_t *idx = nullptr;
+  unsigned long long ng = 0;
+  int rc = HDMR_OK;
+  hipError_t e = hipMallocAsync((void **)&P2, sizeof(double) * (size_t)n * m, s);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&idx, sizeof(int64_t) * (size_t)n, s);
+  if (e != hipSuccess) rc = hip_fail(e, "mlp gate");
+  if (!rc) hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, s, (unsigned long long *)route->d_gate_count);
+  if (!rc && !(rc = forward_rows(route->second, X, n, P2, s))) {
+    hipLaunchKernelGGL(k_gate_rows, dim3(grid_of(n)), dim3(256), 0, s, P, P2, n, m, route->d_mlp_cols, k1,
+                       route->gate_tau, idx, (unsigned long long *)route->d_gate_count);
+    e = hipMemcpyAsync(&ng, route->d_gate_count, sizeof(ng), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = hip_fail(e, "mlp gate");
+  }
+  if (!rc && ng > 0) {
+    e = hipMallocAsync((void **)&Xg, sizeof(double) * (size_t)ng * d, s);
+    if (e == hipSuccess) e = hipMallocAsync((void **)&Ag, sizeof(double) * (size_t)ng * k1, s);
+    if (e != hipSuccess) rc = hip_fail(e, "mlp gate");
+    if (!rc) {
+      hipLaunchKernelGGL(k_gather_rows, dim3(grid_of((int64_t)ng * d)), dim3(256), 0, s, X, idx, (int64_t)ng, d, Xg);
+      rc = hdmr_eval(route->served_full, Xg, (int64_t)ng, Ag, k1, precision, s);
+      if (!rc)
+        hipLaunchKernelGGL(k_scatter_rows, dim3(grid_of((int64_t)ng * k1)), dim3(256), 0, s, Ag, idx, (int64_t)ng, k1,
+                           route->d_mlp_cols, m, Y);
+    }
+  }
+  const_cast<mlp_route *>(route)->last_gated = (int64_t)ng;
+  (void)hipFreeAsync(P2, s);
+  (void)hipFreeAsync(idx, s);
+  (void)hipFreeAsync(Xg, s);
+  (void)hipFreeAsync(Ag, s);
+  return rc;
+}
+
+int mlp_route_set_gate(mlp_route *route, mlp_model *second, const hdmr_model *full, double tau) {
+  clear_error();
+  if (!route || !full || !(tau >= 0.0)) return fail(HDMR_EINVAL, "mlp_route_set_gate: bad argument");
+  if (second && (second->d != route->d || second->m != route->m))
+    return fail(HDMR_EINVAL, "mlp_route_set_gate: the second network's d or m differ");
+  if (full->m != route->m || full->d != route->d) return fail(HDMR_EINVAL, "mlp_route_set_gate: model d or m differ");
+  int rc = set_device(route->net);
+  if (rc) return rc;
+  if (route->served_full) {
+    hdmr_free(route->served_full);
+    route->served_full = nullptr;
+  }
+  route->second = nullptr;
+  if (!second) return HDMR_OK;  // gate off
+  if (!route->mlp_cols.empty() &&
+      (rc = hdmr_model_select(full, 0, nullptr, (int32_t)route->mlp_cols.size(), route->mlp_cols.data(), 1,
+                              &route->served_full)))
+    return rc;
+  if (!route->d_gate_count) HDMR_HIP(hipMalloc((void **)&route->d_gate_count, sizeof(unsigned long long)));
+  route->second = second;
+  route->gate_tau = tau;
+  return HDMR_OK;
+}
+
+int mlp_route_gated(const mlp_route *route, int64_t *n_gated) {
+  clear_error();
+  if (!route || !n_gated) return fail(HDMR_EINVAL, "mlp_route_gated: null argument");
+  *n_gated = route->last_gated;
+  return HDMR_OK;
+}
+
 int mlp_eval_routed(const mlp_route *route, const double *X, int64_t n, double *Y, int32_t precision,
                     hdmr_stream_t stream) {
   clear_error();
@@ -1189,6 +1311,7 @@ int mlp_eval_routed(const mlp_route *route, const double *X, int64_t n, double *
     if (k1 > 0 && !(rc = forward_rows(route->net, X, n, P, s)) &&
         !(rc = hdmr_eval(route->order1, X, n, A, k1, precision, stream)))
       hipLaunchKernelGGL(k_scatter_cols, dim3(grid_of(n * k1)), dim3(256), 0, s, A, k1, route->d_mlp_cols, P, n, m, Y);
+    if (!rc && k1 > 0 && route->second) rc = gate_points(route, X, n, P, Y, precision, s);
     if (!rc && kf > 0 && !(rc = hdmr_eval(route->fallback, X, n, B, kf, precision, stream)))
       hipLaunchKernelGGL(k_scatter_cols, dim3(grid_of(n * kf)), dim3(256), 0, s, B, kf, route->d_fb_cols,
                          (const double *)nullptr, n, m, Y);

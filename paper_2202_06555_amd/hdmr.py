@@ -37,7 +37,7 @@ EXPORTS = (
     # include/hdmr_surrogate.h
     "mlp_param_count", "mlp_create", "mlp_get_params", "mlp_set_standardization", "mlp_fit_standardization",
     "mlp_get_standardization", "mlp_forward", "mlp_loss_grads", "mlp_train", "mlp_free", "hdmr_model_select",
-    "mlp_route_create", "mlp_route_info", "mlp_eval_routed", "mlp_route_free",
+    "mlp_route_create", "mlp_route_info", "mlp_eval_routed", "mlp_route_free", "mlp_route_set_gate", "mlp_route_gated",
 )
 
 _LOCK = threading.Lock()

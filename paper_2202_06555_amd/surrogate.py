@@ -175,3 +175,21 @@ def mlp_route_free(route: Route):
     if route._h and route._h.value:
         lib().mlp_route_free(route._h)
         route._h = ctypes.c_void_p(0)
+
+
+def mlp_route_set_gate(route: Route, second, full: Model, tau):
+    """Per-point ensemble gate (second network or None to switch it off)."""
+    f = lib().mlp_route_set_gate
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double]
+    _check(f(route.handle, second.handle if second is not None else None, full.handle, float(tau)))
+    route._second = second     # the route borrows the network
+
+
+def mlp_route_gated(route: Route) -> int:
+    f = lib().mlp_route_gated
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    n = ctypes.c_int64()
+    _check(f(route.handle, ctypes.byref(n)))
+    return n.value

@@ -228,19 +228,23 @@ def test_model_select(env):
 
 
 def test_surrogate_gain_over_interpolant(env):
-    """What the trained network gains: d=20, m=11, 20 one-dim + 60 two-dim
-    components whose order-2 terms are 100x smaller than the order-1 ones.
-    The network learns the order-2 residual from 2e5 interpolant points; at
-    the tolerance it is validated to (its max-abs error on 5e4 fresh points,
-    every output routed to it) the routed evaluation -- exact order-1 part
-    plus network -- must hold that tolerance on 1e6 other points and run
-    faster than the interpolant alone."""
+    """What the trained network gains, at the surrogate's fixed threshold of
+    1e-4 max-abs: d=20, m=11, 20 one-dim + 60 two-dim components whose
+    order-2 terms are 1000x smaller than the order-1 ones (residual amplitude
+    about 2.6e-4, so the order-1 part alone misses 1e-4).  The network learns
+    the order-2 residual from 2e5 interpolant points; every output validates
+    at <= 1e-4 on 5e4 fresh points and is routed to it; routed evaluation
+    (exact order-1 part plus network) holds 1.5e-4 on 1e6 other points and
+    runs faster than the interpolant alone.  With a second network as a
+    per-point gate at the same threshold, gated points take the interpolant's
+    values."""
     hd, sg = env
     import time
     import torch
+    TAU = 1e-4
     d, m, w = 20, 11, 256
     cfg = ws.config("c2", d=d, m=m, npairs=60, max_level=6)
-    tf = ws.TestFunction(d, m, cfg["pairs"], 11, ref=cfg["anchor"], pair_scale=0.01)
+    tf = ws.TestFunction(d, m, cfg["pairs"], 11, ref=cfg["anchor"], pair_scale=1e-3)
     full = hd.asg_build_components(d, m, cfg["anchor"], (tf.c_fn, tf.c_user), comps=cfg["comps"], max_level=6,
                                    eps_gamma=1e-5)
     c1 = [s for s, S in enumerate(cfg["comps"]) if len(S) == 1]
@@ -248,21 +252,25 @@ def test_surrogate_gain_over_interpolant(env):
     n, steps, B = 200_000, 6000, 1024
     X = _dev(ws.points_for(cfg, n=n, seed=1))
     Yres = hd.hdmr_eval(full, X) - hd.hdmr_eval(o1, X)
-    net = sg.mlp_create(d, w, m, ws.mlp_init_params(d, w, m, seed=0))
-    sg.mlp_fit_standardization(net, Yres)
-    rng = np.random.default_rng(5)
-    order = torch.from_numpy(np.concatenate([rng.permutation(n) for _ in range(steps * B // n + 1)])[:steps * B]
-                             .astype(np.int64)).to("cuda:0")
-    sg.mlp_train(net, X, Yres, order, steps=steps, batch=B, lr0=2e-3, return_losses=False)
-    Xv = _dev(ws.points_for(cfg, n=50_000, seed=3))
-    probe = sg.mlp_route_create(net, full, Xv, 1e30)
-    _, err, _ = sg.mlp_route_info(probe)
-    tau = float(err.max())
     res_max = float(Yres.abs().max())
-    route = sg.mlp_route_create(net, full, Xv, tau)
-    k, _, _ = sg.mlp_route_info(route)
+    assert res_max > 2 * TAU            # the order-1 part alone misses the threshold
+
+    def train(seed):
+        net = sg.mlp_create(d, w, m, ws.mlp_init_params(d, w, m, seed=seed))
+        sg.mlp_fit_standardization(net, Yres)
+        rng = np.random.default_rng(5 + seed)
+        order = torch.from_numpy(np.concatenate([rng.permutation(n) for _ in range(steps * B // n + 1)])
+                                 [:steps * B].astype(np.int64)).to("cuda:0")
+        sg.mlp_train(net, X, Yres, order, steps=steps, batch=B, lr0=2e-3, return_losses=False)
+        return net
+
+    net = train(0)
+    Xv = _dev(ws.points_for(cfg, n=50_000, seed=3))
+    route = sg.mlp_route_create(net, full, Xv, TAU)
+    k, err, _ = sg.mlp_route_info(route)
+    print("validated max-abs per output: max %.2e, median %.2e; residual amplitude %.2e; outputs routed %d of %d"
+          % (err.max(), np.median(err), res_max, k, m))
     assert k == m
-    assert tau <= 0.5 * res_max, (tau, res_max)      # the network carries most of the order-2 part
     Xs = _dev(ws.points_for(cfg, n=1_000_000, seed=2))
 
     def timed(fn, reps=5):
@@ -279,48 +287,66 @@ def test_surrogate_gain_over_interpolant(env):
     Yi, t_interp = timed(lambda: hd.hdmr_eval(full, Xs))
     Yr, t_routed = timed(lambda: sg.mlp_eval_routed(route, Xs))
     fresh = float((Yr - Yi).abs().max())
-    print("tau %.2e (residual max %.2e), fresh-point max-abs %.2e; interpolant %.2f ms, routed %.2f ms: %.2fx"
-          % (tau, res_max, fresh, t_interp * 1e3, t_routed * 1e3, t_interp / t_routed))
-    assert fresh <= 1.5 * tau
+    print("fresh-point max-abs %.2e; interpolant %.2f ms, routed %.2f ms: %.2fx"
+          % (fresh, t_interp * 1e3, t_routed * 1e3, t_interp / t_routed))
+    assert fresh <= 1.5 * TAU
     assert t_interp / t_routed >= 1.5
+    # per-point gate: a second network; points where the two disagree by more
+    # than TAU in an output take the interpolant's values
+    net2 = train(1)
+    sg.mlp_route_set_gate(route, net2, full, TAU)
+    Yg = sg.mlp_eval_routed(route, Xs)
+    torch.cuda.synchronize()
+    ng = sg.mlp_route_gated(route)
+    P1 = sg.mlp_forward(net, Xs)
+    P2 = sg.mlp_forward(net2, Xs)
+    gated = ((P1 - P2).abs() > TAU).any(dim=1)
+    print("gate: %d of %d points take the interpolant" % (ng, Xs.shape[0]))
+    assert ng == int(gated.sum())
+    assert float((Yg[gated] - Yi[gated]).abs().max() if ng else 0.0) <= 1e-12
+    assert float((Yg[~gated] - Yr[~gated]).abs().max()) == 0.0
+    sg.mlp_route_set_gate(route, None, full, TAU)
+    assert float((sg.mlp_eval_routed(route, Xs) - Yr).abs().max()) == 0.0
 
 
 # ---- the GPU network against the exact FP64 network (storage='exact') -------
-# A first-order componentwise error bound of the BF16 kernels, derived from
-# the BF16 unit roundoff u = 2^-9 (round to nearest), FP32 accumulation
-# (gamma_K = K 2^-24 for K products) and the layer widths:
-#   operands: x, the weights and every stored activation / back-propagated
-#   gradient are rounded to BF16 once (relative error <= u each);
-#   a product z = W h + b with BF16 W~, h~ (|h~ - h| <= e) has
-#     |z~ - z| <= |W| e + (2u + gamma_K) |W| |h|        (to first order);
-#   GELU: |gelu'| <= 1.13, |gelu''| <= 0.80, and the stored value adds u |h|.
-# The backward pass propagates the same terms through W^T and gelu'.  The
-# bound is computed from the exact network's magnitudes, so it holds for any
-# rounding point the kernels are allowed to have and fails for a wrong one
-# (an extra BF16 rounding of an FP32 accumulator, a dropped term).
+# Error model of the BF16 kernels, derived from the BF16 unit roundoff
+# u = 2^-9 (round to nearest) and the layer widths K: the input, every weight
+# and every stored activation / back-propagated gradient is rounded to BF16
+# once, a relative perturbation in [-u, u] (variance u^2 / 3), independent
+# between operands; products accumulate in FP32 (2^-24, negligible next to u).
+# Propagating variances through the exact network (rounding errors of the K
+# products of a dot product add in quadrature):
+#   var(dz) = (W*W) var(dh) + (2 u^2 / 3) (W*W)(h*h)
+#   var(dh') = gelu'(z)^2 var(dz) + (u^2 / 3) h'^2        (stored BF16)
+# and the backward pass alike through W^T and gelu' (with gelu''(z) dz for the
+# error of the stored pre-activation).  The bound is 8 standard deviations,
+# about the largest of 10^6 Gaussian samples: the statistical sqrt(K) u
+# analysis of floating-point dot products rather than the worst-case K u.
 
 U = 2.0 ** -9
-LG1, LG2 = 1.13, 0.80
+V = U * U / 3.0
+G2 = 0.80 ** 2      # (max |gelu''|)^2
+NSIG = 8.0
 
 
-def _fwd_bound(layers, X):
+def _fwd_var(layers, X):
     H = np.asarray(X, np.float64)
-    E = U * np.abs(H)
+    VH = V * H * H
     cache = []
     for l, (W, b) in enumerate(layers):
-        K = W.shape[1]
         Z = H @ W.T + b
-        EZ = E @ np.abs(W).T + (2 * U + K * 2.0 ** -24) * (np.abs(H) @ np.abs(W).T) + 2.0 ** -24 * np.abs(b)
-        cache.append((H, E, Z, EZ))
+        VZ = VH @ (W * W).T + 2.0 * V * ((H * H) @ (W * W).T)
+        cache.append((H, VH, Z, VZ))
         if l < 3:
             Hn = omlp.gelu(Z)
-            E = LG1 * EZ + U * (np.abs(Hn) + LG1 * EZ)
+            VH = omlp.gelu_grad(Z) ** 2 * VZ + V * Hn * Hn
             H = Hn
-    return Z, EZ, cache
+    return Z, VZ, cache
 
 
 @pytest.mark.parametrize("d,w,m,n", [(20, 64, 7, 1000), (33, 72, 19, 300), (300, 512, 151, 40000)])
-def test_forward_within_bf16_bound_of_exact_network(env, d, w, m, n):
+def test_forward_within_bf16_error_model_of_exact_network(env, d, w, m, n):
     hd, sg = env
     net, p, mean, std = _net(sg, d, w, m, seed=d + 1)
     X = np.random.default_rng(8).random((n, d))
@@ -329,15 +355,15 @@ def test_forward_within_bf16_bound_of_exact_network(env, d, w, m, n):
     layers = omlp.unpack(p, d, w, m)
     out, _ = omlp.forward(p, X[idx], d, w, m, storage="exact")
     ref = out * std + mean
-    _, EZ, _ = _fwd_bound(layers, X[idx])
-    bound = 1.05 * EZ * std + 2.0 ** -24 * np.abs(ref)   # first-order slack; FP32 output
+    _, VZ, _ = _fwd_var(layers, X[idx])
+    bound = NSIG * np.sqrt(VZ) * std + 2.0 ** -23 * np.abs(ref)   # FP32 output
     ratio = np.abs(Y[idx] - ref) / bound
-    print("forward d=%d w=%d m=%d vs exact network: max |err| / bound = %.3f, max |err| %.2e" %
-          (d, w, m, ratio.max(), np.abs(Y[idx] - ref).max()))
+    print("forward d=%d w=%d m=%d vs exact network: max |err| / bound = %.3f (median %.3f), max |err| %.2e" %
+          (d, w, m, ratio.max(), np.median(ratio), np.abs(Y[idx] - ref).max()))
     assert ratio.max() <= 1.0
 
 
-def test_gradients_within_bf16_bound_of_exact_network(env):
+def test_gradients_within_bf16_error_model_of_exact_network(env):
     hd, sg = env
     import torch
     d, w, m, B = 24, 64, 9, 512
@@ -351,26 +377,24 @@ def test_gradients_within_bf16_bound_of_exact_network(env):
     T = (Yraw[idx] - mu32.astype(np.float64)) / sd32.astype(np.float64)
     rl, rg = omlp.loss_and_grads(p, X[idx], T, d, w, m, storage="exact")
     layers = omlp.unpack(p, d, w, m)
-    out, EZ, cache = _fwd_bound(layers, X[idx])
-    # backward: D = dL/dZ of a layer and its bound ED
+    out, VZ, cache = _fwd_var(layers, X[idx])
+    # backward: D = dL/dZ of a layer and the variance of its stored value
     D = 2.0 * (out - T) / (B * m)
-    ED = 2.0 * EZ / (B * m) + U * np.abs(D)
-    bounds = [None] * 4
+    VD = (2.0 / (B * m)) ** 2 * VZ + V * D * D
+    vars_ = [None] * 4
     for l in range(3, -1, -1):
-        H, E, Z, _ = cache[l]
+        H, VH, Z, _ = cache[l]
         W, _ = layers[l]
-        K = H.shape[0]
-        bounds[l] = (ED.T @ np.abs(H) + np.abs(D).T @ E + K * 2.0 ** -24 * (np.abs(D).T @ np.abs(H)),
-                     ED.sum(axis=0) + K * 2.0 ** -24 * np.abs(D).sum(axis=0))
+        vars_[l] = (VD.T @ (H * H) + (D * D).T @ VH, VD.sum(axis=0))
         if l > 0:
-            Zp, EZp = cache[l - 1][2], cache[l - 1][3]
+            Zp, VZp = cache[l - 1][2], cache[l - 1][3]
             dH = D @ W
-            EdH = ED @ np.abs(W) + (U + W.shape[0] * 2.0 ** -24) * (np.abs(D) @ np.abs(W))
+            VdH = VD @ (W * W) + V * ((D * D) @ (W * W))
             Dn = dH * omlp.gelu_grad(Zp)
-            ED = LG1 * EdH + LG2 * np.abs(dH) * EZp + U * (np.abs(Dn) + LG1 * EdH)
+            VD = omlp.gelu_grad(Zp) ** 2 * VdH + G2 * dH * dH * VZp + V * Dn * Dn
             D = Dn
-    bound = omlp.pack([(1.05 * a, 1.05 * b) for a, b in bounds])
+    bound = omlp.pack([(NSIG * np.sqrt(a), NSIG * np.sqrt(b)) for a, b in vars_]) + 2.0 ** -23 * np.abs(rg)
     ratio = np.abs(g - rg) / np.maximum(bound, 1e-300)
-    print("gradients vs exact network: max |err| / bound = %.3f" % ratio.max())
+    print("gradients vs exact network: max |err| / bound = %.3f (median %.3f)" % (ratio.max(), np.median(ratio)))
     assert ratio.max() <= 1.0
     assert abs(loss - rl) <= 1e-2 * rl
