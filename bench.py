@@ -400,8 +400,7 @@ def bench_batched(args):
     hits = 0
     for i, (g, x, mm) in enumerate(zip(gms, X, meta)):
         hits += hd.hdmr_eval_stats(g, x)[0] * mm["m"]
-        if i % 8 == 7:
-            log("work counted for %d models" % (i + 1))
+        log("work counted for %d models" % (i + 1))
     # path and tile-shape measurement, model by model (the choices persist
     # per model and size bucket; the batched calls below reuse them)
     t0 = time.time()
@@ -644,8 +643,9 @@ def bench_surrogate(args):
     curve = []
     if args.train_seconds > 0:
         # training to a measured plateau: segments of one epoch, each a cosine
-        # decay from a learning rate that shrinks by 0.7 per segment; after
-        # every segment the per-output max-abs error on the validation points
+        # decay from a starting rate that falls log-linearly in wall time from
+        # 1e-3 to 1e-6 over the training budget; after every segment the
+        # per-output max-abs error on the validation points
         seg = max(1, ntr // B)
         lr, k, all_losses = 1e-3, 0, []
         while time.perf_counter() - t0 < args.train_seconds:
@@ -661,7 +661,7 @@ def bench_surrogate(args):
                           "val_max_err_min": float(e.min()), "outputs_at_1e-4": int(kk)})
             log("segment %d: %d steps, %.1f s, loss %.4f, validated max-abs error min %.2e median %.2e max %.2e"
                 % (k, k * seg, curve[-1]["seconds"], curve[-1]["loss"], e.min(), np.median(e), e.max()))
-            lr *= 0.7
+            lr = 1e-3 * 10.0 ** (-3.0 * min(1.0, (time.perf_counter() - t0) / args.train_seconds))
         losses = np.concatenate(all_losses)
         steps = k * seg
     else:
@@ -684,7 +684,9 @@ def bench_surrogate(args):
         "dtype": "bf16 mfma / f32 accumulate (network); f64 (interpolant)", "data": "synthetic",
         "config": {"workload": "d=300, 300 one-dim + 300 two-dim components (order-2 terms x0.01), L=7, "
                                "eps_gamma=1e-4, m=151; width-512 4-layer GELU network trained on %d interpolant "
-                               "pairs (%d epochs, batch 4096); %d served points" % (ntr, args.epochs, ns),
+                               "pairs (%s, batch 4096); %d served points" %
+                               (ntr, ("%d one-epoch segments in %.0f s" % (len(curve), t_train)) if curve
+                                else "%d epochs" % args.epochs, ns),
                    "outputs_on_network": int(k), "validated_max_abs_err": {"min": float(err.min()),
                    "median": float(np.median(err)), "max": float(err.max())},
                    "train_s": t_train, "train_steps": int(steps), "training_curve": curve,

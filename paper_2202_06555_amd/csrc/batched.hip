@@ -12,11 +12,16 @@
 //     later calls;
 //   * mixed-precision models always take the cell-sorted path (the gather
 //     kernel computes in FP64 only);
+//   * the environment variable HDMR_BATCH_PATH=gather|sorted overrides the
+//     measured choice (plain precision; mixed always takes the cell-sorted
+//     path), for diagnostics such as profiling one path alone;
 //   * the persistent launch (queue reset + kernel) is captured once per batch
 //     signature into a hipGraph on a private stream and replayed afterwards;
 //     models on the cell-sorted path run after it on the caller's stream.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <cstring>
 #include <list>
 #include <map>
 #include <mutex>
@@ -267,8 +272,8 @@ int gather_single(const hdmr_model *mdl, const double *X, double *Y, int64_t n, 
   const int64_t units = (n + UNIT_POINTS - 1) / UNIT_POINTS;
   BatchItem *d_item = nullptr;
   unsigned long long *counter = nullptr;
-  HDMR_HIP(hipMallocAsync((void **)&d_item, sizeof(BatchItem), s));
-  HDMR_HIP(hipMallocAsync((void **)&counter, sizeof(unsigned long long), s));
+  HDMR_HIP(dev_malloc_async((void **)&d_item, sizeof(BatchItem), s));
+  HDMR_HIP(dev_malloc_async((void **)&counter, sizeof(unsigned long long), s));
   HDMR_HIP(hipMemcpyAsync(d_item, &I, sizeof(BatchItem), hipMemcpyHostToDevice, s));
   int rc = launch_persistent(d_item, 1, units, counter, mdl->d, s);
   (void)hipFreeAsync(d_item, s);
@@ -373,6 +378,11 @@ extern "C" int hdmr_eval_batched(const hdmr_model *const *models, const double *
   hipStream_t s = (hipStream_t)stream_;
   std::vector<int32_t> choice((size_t)count, PATH_NONE);
   std::vector<char> done((size_t)count, 0);
+  int32_t forced = PATH_NONE;
+  if (const char *env = std::getenv("HDMR_BATCH_PATH")) {
+    if (!std::strcmp(env, "gather")) forced = PATH_GATHER;
+    else if (!std::strcmp(env, "sorted")) forced = PATH_SORTED;
+  }
   // ---- path choice (measured once per model, size bucket and precision) ----
   for (int32_t i = 0; i < count && !rc; ++i) {
     if (n[i] == 0) {
@@ -385,6 +395,10 @@ extern "C" int hdmr_eval_batched(const hdmr_model *const *models, const double *
     }
     if (n[i] < TUNE_MIN_POINTS) {
       choice[i] = PATH_SORTED;  // mixed precision: the cell-sorted path, default tile shape
+      continue;
+    }
+    if (forced != PATH_NONE) {
+      choice[i] = precision == HDMR_MIXED ? PATH_SORTED : forced;
       continue;
     }
     const TuneKey key{models[i], bucket_of(n[i]), precision};
@@ -438,8 +452,8 @@ extern "C" int hdmr_eval_batched(const hdmr_model *const *models, const double *
         host.push_back(I);
         E.models.push_back(models[i]);
       }
-      hipError_t e = hipMalloc((void **)&E.items, sizeof(BatchItem) * host.size());
-      if (e == hipSuccess) e = hipMalloc((void **)&E.counter, sizeof(unsigned long long));
+      hipError_t e = dev_malloc((void **)&E.items, sizeof(BatchItem) * host.size());
+      if (e == hipSuccess) e = dev_malloc((void **)&E.counter, sizeof(unsigned long long));
       if (e == hipSuccess)
         e = hipMemcpy(E.items, host.data(), sizeof(BatchItem) * host.size(), hipMemcpyHostToDevice);
       if (e == hipSuccess && (g_capture == nullptr || g_capture_dev != dev)) {

@@ -24,7 +24,10 @@
 // weights (form 1) of the kept components are gathered into a regular model.
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <limits>
 #include <cstring>
 #include <unordered_map>
@@ -213,7 +216,7 @@ int grow_device(T **ptr, int64_t *cap, int64_t need, int64_t used) {
   int64_t nc = std::max<int64_t>(*cap * 2, 1024);
   while (nc < need) nc *= 2;
   T *np = nullptr;
-  HDMR_HIP(hipMalloc((void **)&np, (size_t)nc * sizeof(T)));
+  HDMR_HIP(dev_malloc((void **)&np, (size_t)nc * sizeof(T)));
   if (*ptr && used > 0) HDMR_HIP(hipMemcpy(np, *ptr, (size_t)used * sizeof(T), hipMemcpyDeviceToDevice));
   if (*ptr) HDMR_HIP(hipFree(*ptr));
   *ptr = np;
@@ -236,6 +239,30 @@ struct DeviceBuffers {
     (void)hipFree(tups);
     (void)hipFree(tab);
     (void)hipFree(alpha);
+  }
+};
+
+// Wall time of the build's phases, printed to stderr at the end of a build
+// when the environment variable HDMR_BUILD_PROFILE is set (diagnostics).
+struct PhaseClock {
+  enum { NODES, ROWS, CALL, NODAL, HIER, DIRECTORY, CHILDREN, QUAD, ASSEMBLE, NPHASE };
+  double sec[NPHASE] = {};
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  void lap(int phase) {
+    const auto t1 = std::chrono::steady_clock::now();
+    sec[phase] += std::chrono::duration<double>(t1 - t0).count();
+    t0 = t1;
+  }
+  void report(int64_t rows, int64_t fcalls) const {
+    if (!std::getenv("HDMR_BUILD_PROFILE")) return;
+    static const char *names[NPHASE] = {"nodes",     "row keys", "f calls",  "nodal values", "hierarchise",
+                                        "directory", "children", "quadrature", "assemble"};
+    double total = 0.0;
+    for (double s : sec) total += s;
+    std::fprintf(stderr, "[hdmr build] %lld grid rows, %lld f rows, %.3f s:", (long long)rows, (long long)fcalls,
+                 total);
+    for (int i = 0; i < NPHASE; ++i) std::fprintf(stderr, " %s %.3f", names[i], sec[i]);
+    std::fprintf(stderr, "\n");
   }
 };
 
@@ -308,6 +335,8 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
   std::vector<TupDesc> h_tups;
   int64_t tab_used = 0, rows_used = 0;
   int32_t lsum_top = P->level_rule == 1 ? P->max_level + KMAX - 1 : P->max_level * KMAX;
+  PhaseClock clk;
+  int64_t f_rows = 0;
   // grows every component of C that has pending nodes (new roots) to the end
   auto run_steps = [&]() -> int {
   const int ncomp = (int)C.size();
@@ -347,6 +376,7 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
       return a.slot < b.slot;
     });
     const int64_t N = (int64_t)nn.size();
+    clk.lap(PhaseClock::NODES);
     // ---- rows to evaluate ----
     std::vector<int64_t> ref((size_t)N << KMAX, -1);   // per node and subset: cache row or -(fresh+2)
     std::vector<RowKey> fresh_keys;
@@ -381,6 +411,7 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
     }
     // ---- one call of f for every new row ----
     const int64_t nfresh = (int64_t)fresh_keys.size(), ncache_new = (int64_t)new_cache_keys.size();
+    clk.lap(PhaseClock::ROWS);
     const int64_t nrows_f = nfresh + ncache_new;
     std::vector<double> X((size_t)nrows_f * d), Y((size_t)nrows_f * m);
     for (int64_t r = 0; r < nrows_f; ++r) {
@@ -392,6 +423,8 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
     if (nrows_f > 0 && f(X.data(), nrows_f, d, Y.data(), m, user) != 0)
       return fail(HDMR_ECALLBACK, "the user function returned an error");
     cache_val.insert(cache_val.end(), Y.begin(), Y.begin() + (size_t)ncache_new * m);
+    f_rows += nrows_f;
+    clk.lap(PhaseClock::CALL);
     // ---- nodal values: g = f(xbar \ x_S), u = nested differences ----
     std::vector<double> yv((size_t)N * M2);
     std::vector<double> buf((size_t)m << KMAX);
@@ -410,6 +443,7 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
             for (int o = 0; o < m; ++o) buf[(size_t)v * m + o] -= buf[(size_t)(v ^ (1 << q)) * m + o];
       for (int o = 0; o < m; ++o) yv[(size_t)j * M2 + m + o] = buf[(size_t)(nsub - 1) * m + o];
     }
+    clk.lap(PhaseClock::NODAL);
     // ---- device: hierarchise against the existing directory ----
     std::vector<NodeDev> nd((size_t)N);
     for (int64_t j = 0; j < N; ++j) {
@@ -442,11 +476,11 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
       (void)hipFree(d_acc);
     };
     hipError_t e = hipSuccess;
-    if ((e = hipMalloc((void **)&d_nodes, sizeof(NodeDev) * N)) != hipSuccess ||
-        (e = hipMalloc((void **)&d_y, sizeof(double) * N * M2)) != hipSuccess ||
-        (e = hipMalloc((void **)&d_ctoff, sizeof(int32_t) * (ncomp + 1))) != hipSuccess ||
-        (e = hipMalloc((void **)&d_ctids, sizeof(int32_t) * std::max<size_t>(ct_ids.size(), 1))) != hipSuccess ||
-        (e = hipMalloc((void **)&d_acc, N)) != hipSuccess ||
+    if ((e = dev_malloc((void **)&d_nodes, sizeof(NodeDev) * N)) != hipSuccess ||
+        (e = dev_malloc((void **)&d_y, sizeof(double) * N * M2)) != hipSuccess ||
+        (e = dev_malloc((void **)&d_ctoff, sizeof(int32_t) * (ncomp + 1))) != hipSuccess ||
+        (e = dev_malloc((void **)&d_ctids, sizeof(int32_t) * std::max<size_t>(ct_ids.size(), 1))) != hipSuccess ||
+        (e = dev_malloc((void **)&d_acc, N)) != hipSuccess ||
         (e = hipMemcpy(d_nodes, nd.data(), sizeof(NodeDev) * N, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(d_y, yv.data(), sizeof(double) * N * M2, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(d_ctoff, ct_off.data(), sizeof(int32_t) * (ncomp + 1), hipMemcpyHostToDevice)) != hipSuccess ||
@@ -472,6 +506,7 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
     }
     cleanup();
     if (e != hipSuccess) return hip_fail(e, "k_hierarchize_fp64");
+    clk.lap(PhaseClock::HIER);
     // ---- register the new rows; append their level multi-indices ----
     std::vector<int32_t> tab_new;
     int64_t t0 = 0;
@@ -546,6 +581,7 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
     if ((rc = grow_device(&D.tups, &D.tups_cap, (int64_t)h_tups.size(), 0))) return rc;
     HDMR_HIP(hipMemcpy(D.tups, h_tups.data(), sizeof(TupDesc) * h_tups.size(), hipMemcpyHostToDevice));
     rows_used += N;
+    clk.lap(PhaseClock::DIRECTORY);
     // ---- children of accepted nodes (Sec. 3.1 exclusion rule) ----
     for (int64_t j = 0; j < N; ++j) {
       if (!acc[j]) continue;
@@ -587,6 +623,7 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
       });
       c.pending.erase(std::unique(c.pending.begin(), c.pending.end()), c.pending.end());
     }
+    clk.lap(PhaseClock::CHILDREN);
   }
   return HDMR_OK;
   };  // run_steps
@@ -653,13 +690,14 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
         qoff.push_back((int64_t)qrow.size());
       }
       std::vector<double> Q((size_t)(ncand * m));
+      clk.lap(PhaseClock::QUAD);
       {
         int64_t *d_row = nullptr, *d_off = nullptr;
         double *d_wt = nullptr, *d_q = nullptr;
-        hipError_t e = hipMalloc((void **)&d_row, sizeof(int64_t) * std::max<size_t>(qrow.size(), 1));
-        if (e == hipSuccess) e = hipMalloc((void **)&d_wt, sizeof(double) * std::max<size_t>(qwt.size(), 1));
-        if (e == hipSuccess) e = hipMalloc((void **)&d_off, sizeof(int64_t) * qoff.size());
-        if (e == hipSuccess) e = hipMalloc((void **)&d_q, sizeof(double) * Q.size());
+        hipError_t e = dev_malloc((void **)&d_row, sizeof(int64_t) * std::max<size_t>(qrow.size(), 1));
+        if (e == hipSuccess) e = dev_malloc((void **)&d_wt, sizeof(double) * std::max<size_t>(qwt.size(), 1));
+        if (e == hipSuccess) e = dev_malloc((void **)&d_off, sizeof(int64_t) * qoff.size());
+        if (e == hipSuccess) e = dev_malloc((void **)&d_q, sizeof(double) * Q.size());
         if (e == hipSuccess && !qrow.empty())
           e = hipMemcpy(d_row, qrow.data(), sizeof(int64_t) * qrow.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess && !qwt.empty())
@@ -707,6 +745,7 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
       const double rho = norm2(sum_k.data()) / denom;
       report_rho.push_back(rho);
       for (int o = 0; o < m; ++o) below[(size_t)o] += sum_k[(size_t)o];
+      clk.lap(PhaseClock::QUAD);
       if (P->eps_rho > 0.0 && !(rho > P->eps_rho)) break;   // continue only while rho > eps_rho
     }
   }
@@ -744,6 +783,8 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
   DeviceAlphaSource src{D.alpha, M2, P->form == 0 ? m : 0};
   int rc = make_model(d, m, c0.data(), hc, out, &src);
   if (rc) return rc;
+  clk.lap(PhaseClock::ASSEMBLE);
+  clk.report(rows_used, f_rows);
   (*out)->ddsg = std::move(report);
   (*out)->ddsg_rho = std::move(report_rho);
   return HDMR_OK;
@@ -789,10 +830,10 @@ extern "C" int hdmr_quadrature(const hdmr_model *model, double *q, double *total
   if (nc > 0) {
     int64_t *d_row = nullptr, *d_off = nullptr;
     double *d_wt = nullptr, *d_q = nullptr;
-    hipError_t e = hipMalloc((void **)&d_row, sizeof(int64_t) * std::max<size_t>(row.size(), 1));
-    if (e == hipSuccess) e = hipMalloc((void **)&d_wt, sizeof(double) * std::max<size_t>(wt.size(), 1));
-    if (e == hipSuccess) e = hipMalloc((void **)&d_off, sizeof(int64_t) * off.size());
-    if (e == hipSuccess) e = hipMalloc((void **)&d_q, sizeof(double) * Q.size());
+    hipError_t e = dev_malloc((void **)&d_row, sizeof(int64_t) * std::max<size_t>(row.size(), 1));
+    if (e == hipSuccess) e = dev_malloc((void **)&d_wt, sizeof(double) * std::max<size_t>(wt.size(), 1));
+    if (e == hipSuccess) e = dev_malloc((void **)&d_off, sizeof(int64_t) * off.size());
+    if (e == hipSuccess) e = dev_malloc((void **)&d_q, sizeof(double) * Q.size());
     if (e == hipSuccess && !row.empty())
       e = hipMemcpy(d_row, row.data(), sizeof(int64_t) * row.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !wt.empty()) e = hipMemcpy(d_wt, wt.data(), sizeof(double) * wt.size(), hipMemcpyHostToDevice);

@@ -440,7 +440,7 @@ int hdmr_eval_stats(const hdmr_model *model, const double *points, int64_t n, in
   const size_t smem = (size_t)M.d * 8 * WAVES_PER_BLOCK;
   if (smem > 65536) return fail(HDMR_EUNSUPPORTED, "d too large for the LDS staging of points");
   unsigned long long *dc = nullptr, hc[2] = {0, 0};
-  HDMR_HIP(hipMalloc((void **)&dc, sizeof(hc)));
+  HDMR_HIP(dev_malloc((void **)&dc, sizeof(hc)));
   hipError_t e = hipMemsetAsync(dc, 0, sizeof(hc), stream);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_count_hits, dim3(grid_for(n)), dim3(WAVE * WAVES_PER_BLOCK), smem, stream, M, points, n, dc);
@@ -468,7 +468,7 @@ int hdmr_eval_grad(const hdmr_model *model, const double *points, int64_t n, dou
   if (use_sorted_path(model, n)) {
     // values are produced alongside; a scratch buffer stands in when not wanted
     double *F = values;
-    if (!F) HDMR_HIP(hipMallocAsync((void **)&F, sizeof(double) * (size_t)n * model->m, stream));
+    if (!F) HDMR_HIP(dev_malloc_async((void **)&F, sizeof(double) * (size_t)n * model->m, stream));
     rc = eval_sorted(model, points, n, F, HDMR_PLAIN_FP64, stream, 0, grad);
     if (!values) (void)hipFreeAsync(F, stream);
     return rc;

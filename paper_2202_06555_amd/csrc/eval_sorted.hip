@@ -67,6 +67,8 @@ constexpr int TR_MIXED_ALT = 32;
 constexpr int TILE_GRID = HDMR_TILE_GRID;  // most workgroups of a contraction launch
 constexpr int CHUNK = HDMR_CHUNK;          // points per work item (<= 4 sub-tiles)
 constexpr int CHUNK_MIN = 64;              // smallest work item a tile shape may ask for
+constexpr int NBUF = 3;                    // pass buffer sets in flight
+constexpr int NEVENTS = 2 + 2 * NBUF;      // ready, side end, sorted[NBUF], done[NBUF]
 
 __global__ void k_transpose(const double *__restrict__ X, int64_t n, int d, double *__restrict__ XT,
                             uint8_t *__restrict__ nanflag) {
@@ -167,6 +169,7 @@ __global__ void k_write_tiles(const uint32_t *__restrict__ start, const uint32_t
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 // A row of a cell as the contraction needs it (32 bytes).  w is the
 // component weight w_S in FP64, as the model stores it.
@@ -438,10 +441,24 @@ __device__ __forceinline__ uint4 tile_rec(const uint4 *__restrict__ tiles, int64
 // writer and passes are stream-ordered launches, so plain loads and stores
 // suffice.
 
-constexpr int OS64 = 66;  // parked FP64 sums: row stride (doubles)
 constexpr int OS32 = 68;  // parked FP32 sums: row stride (floats)
 
-// Adds the parked sums of a sub-tile (s_o[pt * OS64 + c], c < ncols) to the
+// LDS layouts of the FP64 kernel, both free of bank conflicts for 64-lane
+// 8-byte accesses whether the banks serve 16 or 32 lanes per cycle.
+// Weights in MFMA-operand order: the 16 x 4 A block of point group g and
+// k-step j is 64 consecutive doubles, lane (kk, jj) at kk * 16 + jj, so the
+// A-operand reads are linear in the lane; the writes (thread pt = t / 4 of a
+// wave's 16 points, row r = t % 4 + 4 i) cover one 64-double block each.
+template <int TR>
+__device__ __forceinline__ int w_off(int pt, int r) {
+  return (pt >> 4) * (16 * TR) + (r >> 2) * 64 + (r & 3) * 16 + (pt & 15);
+}
+// Parked sums: 64 doubles per point, columns of odd points swizzled by 16, so
+// that the two 16-lane halves of a parking store (points of opposite parity)
+// fall on disjoint banks; a (2c, 2c + 1) pair stays adjacent.
+__device__ __forceinline__ int p_off(int pt, int c) { return pt * 64 + (c ^ ((pt & 1) << 4)); }
+
+// Adds the parked sums of a sub-tile (s_o at p_off(pt, c), c < ncols) to the
 // FP64 accumulator rows acc + pid[pt] * AS + o0: 16-byte pieces, all loads of
 // a thread in flight before its stores.  NARROW: ncols == 16.
 template <bool NARROW>
@@ -466,8 +483,9 @@ __device__ __forceinline__ void add_parked_f64(double *__restrict__ acc, int AS,
     const int pt = pr + PR * i;
     if (p[i] >= 0) {
       double2 r = v[i];
-      r.x += s_o[pt * OS64 + 2 * c2];
-      r.y += s_o[pt * OS64 + 2 * c2 + 1];
+      const double2 s = *reinterpret_cast<const double2 *>(s_o + p_off(pt, 2 * c2));
+      r.x += s.x;
+      r.y += s.y;
       *reinterpret_cast<double2 *>(base + (int64_t)p[i] * AS) = r;
     }
   }
@@ -564,9 +582,8 @@ __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const
                                                       const int32_t *__restrict__ spid, const double *__restrict__ xk,
                                                       int64_t n, double *__restrict__ acc, int AS, int o0,
                                                       double *__restrict__ G) {
-  constexpr int WS = TR + 4;  // W row stride (doubles): spreads A-operand reads over the LDS banks
-  constexpr int SWN = (TPTS * WS > TPTS * OS64) ? TPTS * WS : TPTS * OS64;
-  __shared__ double s_w[SWN];  // weights [TPTS][WS], then the parked sums [TPTS][OS64]
+  constexpr int SWN = (TPTS * TR > TPTS * 64) ? TPTS * TR : TPTS * 64;
+  __shared__ __attribute__((aligned(16))) double s_w[SWN];  // weights (w_off), then the parked sums (p_off)
   __shared__ RowsLds<TR> s_rows[2];
   __shared__ PtsLds s_pts[2];
   const int t = threadIdx.x, lane = t & (WAVE - 1), wid = t / WAVE;
@@ -648,7 +665,7 @@ __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const
           const double x0 = SP.xs[pt][0], x1 = SP.xs[pt][1], x2 = SP.xs[pt][2], x3 = SP.xs[pt][3];
 #pragma unroll 2
           for (int r = grp; r < Rp; r += 4)
-            s_w[pt * WS + r] = (r < Rb && pt < cnt) ? row_weight(SR.rows[r], SR.ix[r], x0, x1, x2, x3) : 0.0;
+            s_w[w_off<TR>(pt, r)] = (r < Rb && pt < cnt) ? row_weight(SR.rows[r], SR.ix[r], x0, x1, x2, x3) : 0.0;
         }
         store_pts(s_pts[pb ^ 1], pn, t);
         if (last) store_rows<TR>(s_rows[rb ^ 1], rn, t);
@@ -663,7 +680,7 @@ __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const
 #pragma unroll
             for (int j = 0; j < TR / 4; ++j)
               if (4 * j < Rp)
-                a4[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[(wid * 16 + jj) * WS + 4 * j + kk], b[j], a4[0], 0, 0,
+                a4[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[wid * 16 * TR + j * 64 + lane], b[j], a4[0], 0, 0,
                                                              0);
           }
         } else if (wave_on) {
@@ -672,7 +689,7 @@ __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const
             if (4 * j < Rp) {
 #pragma unroll
               for (int mt = 0; mt < 4; ++mt)
-                a4[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[(mt * 16 + jj) * WS + 4 * j + kk], b[j], a4[mt], 0,
+                a4[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[mt * 16 * TR + j * 64 + lane], b[j], a4[mt], 0,
                                                               0, 0);
               // bound how far A-operand loads are hoisted (register pressure)
               __builtin_amdgcn_sched_barrier(0);
@@ -683,12 +700,12 @@ __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const
         // park: lane holds rows kk + 4 i of each 16-point group, column jj
         if constexpr (NARROW) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) s_w[(wid * 16 + kk + 4 * i) * OS64 + jj] = a4[0][i];
+          for (int i = 0; i < 4; ++i) s_w[p_off(wid * 16 + kk + 4 * i, jj)] = a4[0][i];
         } else if (wave_on) {
 #pragma unroll
           for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) s_w[(mt * 16 + kk + 4 * i) * OS64 + wid * 16 + jj] = a4[mt][i];
+            for (int i = 0; i < 4; ++i) s_w[p_off(mt * 16 + kk + 4 * i, wid * 16 + jj)] = a4[mt][i];
         }
         __syncthreads();
         add_parked_f64<NARROW>(acc, AS, o0, ncols, SP.pid, cnt, s_w, t);
@@ -701,7 +718,7 @@ __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const
               const int pt = t >> 2, grp = t & 3;
               const double x0 = SP.xs[pt][0], x1 = SP.xs[pt][1], x2 = SP.xs[pt][2], x3 = SP.xs[pt][3];
               for (int r = grp; r < Rp; r += 4)
-                s_w[pt * WS + r] = (r < Rb && pt < cnt) ? row_dweight(SR.rows[r], SR.ix[r], x0, x1, x2, x3, q) : 0.0;
+                s_w[w_off<TR>(pt, r)] = (r < Rb && pt < cnt) ? row_dweight(SR.rows[r], SR.ix[r], x0, x1, x2, x3, q) : 0.0;
             }
             __syncthreads();
 #pragma unroll
@@ -710,7 +727,7 @@ __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const
 #pragma unroll
               for (int j = 0; j < TR / 4; ++j)
                 if (4 * j < Rp)
-                  a4[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[(wid * 16 + jj) * WS + 4 * j + kk], b[j], a4[0], 0,
+                  a4[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[wid * 16 * TR + j * 64 + lane], b[j], a4[0], 0,
                                                                0, 0);
               if (col < m)
                 add_group(G + (int64_t)P.dims[q] * m, SP.pid, (int64_t)M.d * m, col, cnt, wid * 16 + kk, 4, a4[0]);
@@ -720,7 +737,7 @@ __global__ __launch_bounds__(256, 3) void k_tile_fp64(ModelView M, Pass P, const
                 if (4 * j < Rp) {
 #pragma unroll
                   for (int mt = 0; mt < 4; ++mt)
-                    a4[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[(mt * 16 + jj) * WS + 4 * j + kk], b[j], a4[mt],
+                    a4[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_w[mt * 16 * TR + j * 64 + lane], b[j], a4[mt],
                                                                   0, 0, 0);
                   __builtin_amdgcn_sched_barrier(0);
                 }
@@ -848,16 +865,23 @@ __global__ __launch_bounds__(256, 3) void k_tile_mixed(ModelView M, Pass P, cons
         const PtsLds &SP = s_pts[pb];
         const int cnt = min(count - sub * TPTS, TPTS);
         {
+          // thread (pt = t / 4, group t % 4) forms row pairs 2 group + 8 i and
+          // writes each plane's pair as one 4-byte word (the 64 lanes of a
+          // store cover 64 distinct banks)
           const int pt = t >> 2, grp = t & 3;
           const double x0 = SP.xs[pt][0], x1 = SP.xs[pt][1], x2 = SP.xs[pt][2], x3 = SP.xs[pt][3];
 #pragma unroll 2
-          for (int r = grp; r < Rp; r += 4) {
-            const float v = (r < Rb && pt < cnt) ? (float)row_weight(SR.rows[r], SR.ix[r], x0, x1, x2, x3) : 0.f;
-            __bf16 h, md, l;
-            split_bf16(v, h, md, l);
-            s_w[(0 * TPTS + pt) * WS + r] = h;
-            s_w[(1 * TPTS + pt) * WS + r] = md;
-            s_w[(2 * TPTS + pt) * WS + r] = l;
+          for (int r = 2 * grp; r < Rp; r += 8) {
+            const bool on = pt < cnt;
+            const float v0 = (r < Rb && on) ? (float)row_weight(SR.rows[r], SR.ix[r], x0, x1, x2, x3) : 0.f;
+            const float v1 = (r + 1 < Rb && on) ? (float)row_weight(SR.rows[r + 1], SR.ix[r + 1], x0, x1, x2, x3) : 0.f;
+            __bf16 h0, m0, l0, h1, m1, l1;
+            split_bf16(v0, h0, m0, l0);
+            split_bf16(v1, h1, m1, l1);
+            const bf16x2 h = {h0, h1}, md = {m0, m1}, l = {l0, l1};
+            *reinterpret_cast<bf16x2 *>(&s_w[(0 * TPTS + pt) * WS + r]) = h;
+            *reinterpret_cast<bf16x2 *>(&s_w[(1 * TPTS + pt) * WS + r]) = md;
+            *reinterpret_cast<bf16x2 *>(&s_w[(2 * TPTS + pt) * WS + r]) = l;
           }
         }
         store_pts(s_pts[pb ^ 1], pn, t);
@@ -960,8 +984,11 @@ struct Carve {
   }
 };
 
-// Buffers of one pass in flight (two sets: the keys, sort and row discovery
-// of the next pass run on a second stream while this pass contracts).
+// Buffers of one pass in flight.  NBUF sets: the keys, sort and row
+// discovery of the next passes run on a second stream while this pass
+// contracts, up to NBUF - 1 passes ahead.  The second stream's kernels get
+// compute units mostly as the contraction's workgroups retire, so the extra
+// pass of slack lets them finish before the contraction needs them.
 struct PassBufs {
   uint16_t *key, *key_s;
   int32_t *idx, *spid;
@@ -976,7 +1003,7 @@ struct Workspace {
   double *xt, *acc;
   float *acc32;
   uint8_t *nanflag;
-  PassBufs pb[2];
+  PassBufs pb[NBUF];
   size_t tmp_bytes;
 };
 
@@ -1054,7 +1081,7 @@ static __device__ __align__(256) char scratch[NOALLOC_BYTES];
 namespace {
 struct NoallocDev {
   void *ptr = nullptr;
-  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[NEVENTS] = {};
 };
 std::mutex g_noalloc_mu;
 std::vector<NoallocDev> g_noalloc;
@@ -1117,7 +1144,7 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
   char *base = nullptr;
   const bool own = ws_base == nullptr;
   if (own) {
-    HDMR_HIP(hipMallocAsync((void **)&base, need, stream));
+    HDMR_HIP(dev_malloc_async((void **)&base, need, stream));
   } else {
     if (ws_bytes < need)
       return fail(HDMR_EINVAL, "workspace of " + std::to_string(ws_bytes) + " bytes is below the " +
@@ -1128,11 +1155,16 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
   C.base = base;
   carve_workspace(C, W, n, d, AS, mixed, list_max, tmp_bytes);
   hipStream_t side = side_stream(model->device);
-  hipEvent_t ev_ready = nullptr, ev_side_end = nullptr, ev_sorted[2] = {nullptr, nullptr},
-             ev_done[2] = {nullptr, nullptr};
+  hipEvent_t ev_ready = nullptr, ev_side_end = nullptr, ev_sorted[NBUF] = {}, ev_done[NBUF] = {};
   hipError_t e = side ? hipSuccess : hipErrorInvalidValue;
-  hipEvent_t *evs[6] = {&ev_ready, &ev_side_end, &ev_sorted[0], &ev_sorted[1], &ev_done[0], &ev_done[1]};
-  for (int i = 0; i < 6; ++i) {
+  hipEvent_t *evs[NEVENTS];
+  evs[0] = &ev_ready;
+  evs[1] = &ev_side_end;
+  for (int i = 0; i < NBUF; ++i) {
+    evs[2 + i] = &ev_sorted[i];
+    evs[2 + NBUF + i] = &ev_done[i];
+  }
+  for (int i = 0; i < NEVENTS; ++i) {
     if (events)
       *evs[i] = events[i];  // the caller's persistent events
     else if (e == hipSuccess)
@@ -1166,14 +1198,14 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
   int since_fold = 0;
   for (size_t pi = 0; pi < model->passes.size() && e == hipSuccess; ++pi) {
     const Pass &P = model->passes[pi];
-    const int bsel = (int)(pi & 1);
+    const int bsel = (int)(pi % NBUF);
     PassBufs &B = W.pb[bsel];
     const int nbins = 1 << P.key_bits;
     const unsigned gb = (unsigned)((nbins + 255) / 256);
     const unsigned gc = (unsigned)std::min((nbins + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, 8192);
     // keys, sort and row discovery of this pass on the second stream, once
-    // the contraction two passes back is done with this buffer set
-    if (pi >= 2 && (e = hipStreamWaitEvent(side, ev_done[bsel], 0)) != hipSuccess) break;
+    // the contraction NBUF passes back is done with this buffer set
+    if (pi >= NBUF && (e = hipStreamWaitEvent(side, ev_done[bsel], 0)) != hipSuccess) break;
     {
       StageTimer tm(STAGE_SORT, side);
       hipLaunchKernelGGL(k_keys, dim3(gs), dim3(256), 0, side, W.xt, n, P, B.key, B.idx, B.xk);
@@ -1256,8 +1288,8 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
     e = hipGetLastError();
   }
   if (!events)
-    for (hipEvent_t ev : {ev_ready, ev_side_end, ev_sorted[0], ev_sorted[1], ev_done[0], ev_done[1]})
-      if (ev) (void)hipEventDestroy(ev);
+    for (int i = 0; i < NEVENTS; ++i)
+      if (*evs[i]) (void)hipEventDestroy(*evs[i]);
   if (own) (void)hipFreeAsync(base, stream);
   if (e != hipSuccess) return hip_fail(e, "sorted evaluation");
   return HDMR_OK;

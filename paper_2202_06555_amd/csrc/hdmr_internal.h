@@ -123,6 +123,14 @@ namespace hdmr {
 // thread-local error message + status helpers
 int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
+
+// Every device allocation of the library goes through these two (model.hip).
+// For error-path tests a failure can be forced from the host: with the
+// environment variable HDMR_FAIL_ALLOC=k (k >= 0), the allocation numbered k
+// (from 0, counted since the variable last changed value) returns
+// hipErrorOutOfMemory without allocating.
+hipError_t dev_malloc(void **p, size_t bytes);
+hipError_t dev_malloc_async(void **p, size_t bytes, hipStream_t s);
 void clear_error();
 
 #define HDMR_HIP(call)                                   \
@@ -161,7 +169,7 @@ void keep_pool_memory(int device);
 // gradient is computed as well.
 // ws_base (device, ws_bytes bytes) supplies the workspace; with NULL it is
 // allocated stream-ordered on the device's pool and released at the end.
-// events (6, optional): persistent events to use instead of per-call ones.
+// events (8, optional): persistent events to use instead of per-call ones.
 int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, int precision, hipStream_t stream,
                 int variant = 0, double *G = nullptr, void *ws_base = nullptr, size_t ws_bytes = 0,
                 hipEvent_t *events = nullptr);

@@ -145,8 +145,8 @@ extern "C" int irbc_residuals(const hdmr_model *policy, const irbc_params *param
   const int64_t chunk = std::max<int64_t>(1, ((int64_t)1 << 21) / P.Q);
   const int64_t nc = std::min<int64_t>(n, chunk);
   double *Xn = nullptr, *Pn = nullptr;
-  HDMR_HIP(hipMallocAsync((void **)&Xn, sizeof(double) * (size_t)(nc * P.Q * d), stream));
-  hipError_t e = hipMallocAsync((void **)&Pn, sizeof(double) * (size_t)(nc * P.Q * m), stream);
+  HDMR_HIP(dev_malloc_async((void **)&Xn, sizeof(double) * (size_t)(nc * P.Q * d), stream));
+  hipError_t e = dev_malloc_async((void **)&Pn, sizeof(double) * (size_t)(nc * P.Q * m), stream);
   if (e != hipSuccess) {
     (void)hipFreeAsync(Xn, stream);
     return hip_fail(e, "irbc_residuals workspace");
@@ -383,7 +383,7 @@ extern "C" int irbc_solve(const hdmr_model *policy, const irbc_params *params, c
                     sizeof(double) * (size_t)(n * M), sizeof(double) * (size_t)n, sizeof(double)};
   double **ptrs[] = {&Xs, &Cs, &Rs, &h, &J, &rhs, &dx, &rmax, &dmax};
   hipError_t e = hipSuccess;
-  for (int i = 0; i < 9 && e == hipSuccess; ++i) e = hipMallocAsync((void **)ptrs[i], bytes[i], stream);
+  for (int i = 0; i < 9 && e == hipSuccess; ++i) e = dev_malloc_async((void **)ptrs[i], bytes[i], stream);
   auto release = [&]() {
     for (double **p : ptrs)
       if (*p) (void)hipFreeAsync(*p, stream);
@@ -432,8 +432,8 @@ extern "C" int irbc_euler_errors(const hdmr_model *policy, const irbc_params *pa
   if (rc) return rc;
   hipStream_t stream = (hipStream_t)stream_;
   double *C = nullptr, *R = nullptr;
-  HDMR_HIP(hipMallocAsync((void **)&C, sizeof(double) * (size_t)(n * M), stream));
-  hipError_t e = hipMallocAsync((void **)&R, sizeof(double) * (size_t)(n * M), stream);
+  HDMR_HIP(dev_malloc_async((void **)&C, sizeof(double) * (size_t)(n * M), stream));
+  hipError_t e = dev_malloc_async((void **)&R, sizeof(double) * (size_t)(n * M), stream);
   if (e != hipSuccess) {
     (void)hipFreeAsync(C, stream);
     return hip_fail(e, "irbc_euler_errors workspace");
@@ -467,8 +467,8 @@ int solve_callback(const double *X, int64_t n, int32_t d, double *Y, int32_t m, 
   StepCtx &S = *static_cast<StepCtx *>(user);
   double *dX = nullptr, *dY = nullptr;
   hipStream_t st = (hipStream_t)0;
-  if (hipMalloc((void **)&dX, sizeof(double) * (size_t)(n * d)) != hipSuccess) return -1;
-  if (hipMalloc((void **)&dY, sizeof(double) * (size_t)(n * m)) != hipSuccess) {
+  if (dev_malloc((void **)&dX, sizeof(double) * (size_t)(n * d)) != hipSuccess) return -1;
+  if (dev_malloc((void **)&dY, sizeof(double) * (size_t)(n * m)) != hipSuccess) {
     (void)hipFree(dX);
     return -1;
   }

@@ -694,11 +694,11 @@ struct mlp_model {
     outv = tgt = nullptr;
     cap = 0;
     const int64_t gw = pad8(std::max(w, m));
-    for (int l = 0; l < NL; ++l) HDMR_HIP(hipMalloc((void **)&h[l], sizeof(bf16) * rows * ldin[l]));
-    for (int l = 0; l < NL - 1; ++l) HDMR_HIP(hipMalloc((void **)&z[l], sizeof(float) * rows * w));
-    for (int q = 0; q < 2; ++q) HDMR_HIP(hipMalloc((void **)&gb[q], sizeof(bf16) * rows * gw));
-    HDMR_HIP(hipMalloc((void **)&outv, sizeof(float) * rows * pad8(m)));
-    HDMR_HIP(hipMalloc((void **)&tgt, sizeof(float) * rows * m));
+    for (int l = 0; l < NL; ++l) HDMR_HIP(dev_malloc((void **)&h[l], sizeof(bf16) * rows * ldin[l]));
+    for (int l = 0; l < NL - 1; ++l) HDMR_HIP(dev_malloc((void **)&z[l], sizeof(float) * rows * w));
+    for (int q = 0; q < 2; ++q) HDMR_HIP(dev_malloc((void **)&gb[q], sizeof(bf16) * rows * gw));
+    HDMR_HIP(dev_malloc((void **)&outv, sizeof(float) * rows * pad8(m)));
+    HDMR_HIP(dev_malloc((void **)&tgt, sizeof(float) * rows * m));
     cap = rows;
     return HDMR_OK;
   }
@@ -908,16 +908,16 @@ int mlp_create(int32_t d, int32_t width, int32_t m, const float *params, mlp_mod
   }
   net->nparam = o;
   hipError_t e = hipGetDevice(&net->device);
-  if (e == hipSuccess) e = hipMalloc((void **)&net->p, sizeof(float) * o);
-  if (e == hipSuccess) e = hipMalloc((void **)&net->g, sizeof(float) * o);
-  if (e == hipSuccess) e = hipMalloc((void **)&net->mom, sizeof(float) * o);
-  if (e == hipSuccess) e = hipMalloc((void **)&net->vel, sizeof(float) * o);
-  if (e == hipSuccess) e = hipMalloc((void **)&net->mean, sizeof(float) * m);
-  if (e == hipSuccess) e = hipMalloc((void **)&net->stdv, sizeof(float) * m);
-  if (e == hipSuccess) e = hipMalloc((void **)&net->loss, sizeof(float) * 1);
+  if (e == hipSuccess) e = dev_malloc((void **)&net->p, sizeof(float) * o);
+  if (e == hipSuccess) e = dev_malloc((void **)&net->g, sizeof(float) * o);
+  if (e == hipSuccess) e = dev_malloc((void **)&net->mom, sizeof(float) * o);
+  if (e == hipSuccess) e = dev_malloc((void **)&net->vel, sizeof(float) * o);
+  if (e == hipSuccess) e = dev_malloc((void **)&net->mean, sizeof(float) * m);
+  if (e == hipSuccess) e = dev_malloc((void **)&net->stdv, sizeof(float) * m);
+  if (e == hipSuccess) e = dev_malloc((void **)&net->loss, sizeof(float) * 1);
   net->loss_cap = 1;
   for (int l = 0; l < NL && e == hipSuccess; ++l)
-    e = hipMalloc((void **)&net->wb[l], sizeof(bf16) * net->out[l] * net->ldin[l]);
+    e = dev_malloc((void **)&net->wb[l], sizeof(bf16) * net->out[l] * net->ldin[l]);
   // only layers whose weight gradient is split need slices (wide layers fill
   // the chip unsplit)
   int64_t wsl = (int64_t)COLSUM_CHUNKS * std::max(width, m);
@@ -925,7 +925,7 @@ int mlp_create(int32_t d, int32_t width, int32_t m, const float *params, mlp_mod
     const int64_t want = dw_split(net->out[l], net->in[l]);
     if (want > 1) wsl = std::max<int64_t>(wsl, want * net->out[l] * net->in[l]);
   }
-  if (e == hipSuccess) e = hipMalloc((void **)&net->ws, sizeof(float) * wsl);
+  if (e == hipSuccess) e = dev_malloc((void **)&net->ws, sizeof(float) * wsl);
   net->ws_len = wsl;
   if (e == hipSuccess) e = hipMemcpy(net->p, params, sizeof(float) * o, hipMemcpyHostToDevice);
   if (e == hipSuccess) {
@@ -1042,7 +1042,7 @@ int mlp_train(mlp_model *net, const double *X, const double *Y, const int64_t *o
     (void)hipFree(net->loss);
     net->loss = nullptr;
     net->loss_cap = 0;
-    HDMR_HIP(hipMalloc((void **)&net->loss, sizeof(float) * steps));
+    HDMR_HIP(dev_malloc((void **)&net->loss, sizeof(float) * steps));
     net->loss_cap = steps;
   }
   hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(net->loss_cap)), dim3(256), 0, s, net->loss, net->loss_cap, 0.f);
@@ -1149,10 +1149,10 @@ int mlp_route_create(mlp_model *net, const hdmr_model *full, const double *Xval,
   if ((rc = hdmr_model_select(full, (int32_t)c1.size(), c1.data(), 0, nullptr, 1, &o1all))) return rc;
   double *F = nullptr, *A = nullptr, *P = nullptr, *E = nullptr;
   const size_t bytes = sizeof(double) * (size_t)nval * m;
-  hipError_t e = hipMalloc((void **)&F, bytes);
-  if (e == hipSuccess) e = hipMalloc((void **)&A, bytes);
-  if (e == hipSuccess) e = hipMalloc((void **)&P, bytes);
-  if (e == hipSuccess) e = hipMalloc((void **)&E, sizeof(double) * m);
+  hipError_t e = dev_malloc((void **)&F, bytes);
+  if (e == hipSuccess) e = dev_malloc((void **)&A, bytes);
+  if (e == hipSuccess) e = dev_malloc((void **)&P, bytes);
+  if (e == hipSuccess) e = dev_malloc((void **)&E, sizeof(double) * m);
   mlp_route *R = nullptr;
   if (e != hipSuccess) {
     rc = hip_fail(e, "mlp_route_create");
@@ -1189,8 +1189,8 @@ int mlp_route_create(mlp_model *net, const hdmr_model *full, const double *Xval,
   if (!rc && !R->fb_cols.empty())
     rc = hdmr_model_select(full, 0, nullptr, (int32_t)R->fb_cols.size(), R->fb_cols.data(), 1, &R->fallback);
   if (!rc) {
-    e = hipMalloc((void **)&R->d_mlp_cols, sizeof(int32_t) * std::max<size_t>(1, R->mlp_cols.size()));
-    if (e == hipSuccess) e = hipMalloc((void **)&R->d_fb_cols, sizeof(int32_t) * std::max<size_t>(1, R->fb_cols.size()));
+    e = dev_malloc((void **)&R->d_mlp_cols, sizeof(int32_t) * std::max<size_t>(1, R->mlp_cols.size()));
+    if (e == hipSuccess) e = dev_malloc((void **)&R->d_fb_cols, sizeof(int32_t) * std::max<size_t>(1, R->fb_cols.size()));
     if (e == hipSuccess && !R->mlp_cols.empty())
       e = hipMemcpy(R->d_mlp_cols, R->mlp_cols.data(), sizeof(int32_t) * R->mlp_cols.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !R->fb_cols.empty())
@@ -1225,8 +1225,8 @@ static int gate_points(const mlp_route *route, const double *X, int64_t n, const
   int64_t *idx = nullptr;
   unsigned long long ng = 0;
   int rc = HDMR_OK;
-  hipError_t e = hipMallocAsync((void **)&P2, sizeof(double) * (size_t)n * m, s);
-  if (e == hipSuccess) e = hipMallocAsync((void **)&idx, sizeof(int64_t) * (size_t)n, s);
+  hipError_t e = dev_malloc_async((void **)&P2, sizeof(double) * (size_t)n * m, s);
+  if (e == hipSuccess) e = dev_malloc_async((void **)&idx, sizeof(int64_t) * (size_t)n, s);
   if (e != hipSuccess) rc = hip_fail(e, "mlp gate");
   if (!rc) hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, s, (unsigned long long *)route->d_gate_count);
   if (!rc && !(rc = forward_rows(route->second, X, n, P2, s))) {
@@ -1237,8 +1237,8 @@ static int gate_points(const mlp_route *route, const double *X, int64_t n, const
     if (e != hipSuccess) rc = hip_fail(e, "mlp gate");
   }
   if (!rc && ng > 0) {
-    e = hipMallocAsync((void **)&Xg, sizeof(double) * (size_t)ng * d, s);
-    if (e == hipSuccess) e = hipMallocAsync((void **)&Ag, sizeof(double) * (size_t)ng * k1, s);
+    e = dev_malloc_async((void **)&Xg, sizeof(double) * (size_t)ng * d, s);
+    if (e == hipSuccess) e = dev_malloc_async((void **)&Ag, sizeof(double) * (size_t)ng * k1, s);
     if (e != hipSuccess) rc = hip_fail(e, "mlp gate");
     if (!rc) {
       hipLaunchKernelGGL(k_gather_rows, dim3(grid_of((int64_t)ng * d)), dim3(256), 0, s, X, idx, (int64_t)ng, d, Xg);
@@ -1274,7 +1274,7 @@ int mlp_route_set_gate(mlp_route *route, mlp_model *second, const hdmr_model *fu
       (rc = hdmr_model_select(full, 0, nullptr, (int32_t)route->mlp_cols.size(), route->mlp_cols.data(), 1,
                               &route->served_full)))
     return rc;
-  if (!route->d_gate_count) HDMR_HIP(hipMalloc((void **)&route->d_gate_count, sizeof(unsigned long long)));
+  if (!route->d_gate_count) HDMR_HIP(dev_malloc((void **)&route->d_gate_count, sizeof(unsigned long long)));
   route->second = second;
   route->gate_tau = tau;
   return HDMR_OK;
@@ -1301,10 +1301,10 @@ int mlp_eval_routed(const mlp_route *route, const double *X, int64_t n, double *
   double *P = nullptr, *A = nullptr, *B = nullptr;
   hipError_t e = hipSuccess;
   if (k1 > 0) {
-    e = hipMallocAsync((void **)&P, sizeof(double) * (size_t)n * m, s);
-    if (e == hipSuccess) e = hipMallocAsync((void **)&A, sizeof(double) * (size_t)n * k1, s);
+    e = dev_malloc_async((void **)&P, sizeof(double) * (size_t)n * m, s);
+    if (e == hipSuccess) e = dev_malloc_async((void **)&A, sizeof(double) * (size_t)n * k1, s);
   }
-  if (e == hipSuccess && kf > 0) e = hipMallocAsync((void **)&B, sizeof(double) * (size_t)n * kf, s);
+  if (e == hipSuccess && kf > 0) e = dev_malloc_async((void **)&B, sizeof(double) * (size_t)n * kf, s);
   if (e != hipSuccess) {
     rc = hip_fail(e, "mlp_eval_routed");
   } else {

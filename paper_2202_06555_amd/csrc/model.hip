@@ -2,6 +2,7 @@
 // per-level-multi-index lookup directory, upload to HBM, export, errors.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -23,6 +24,43 @@ int hip_fail(hipError_t e, const char *what) {
 }
 
 void clear_error() { g_last_error.clear(); }
+
+namespace {
+std::mutex g_inject_mu;
+std::string g_inject_val;
+int64_t g_inject_count = 0;
+
+bool injected_alloc_failure() {
+  const char *v = std::getenv("HDMR_FAIL_ALLOC");
+  const std::string s = v ? v : "";
+  std::lock_guard<std::mutex> lk(g_inject_mu);
+  if (s != g_inject_val) {
+    g_inject_val = s;
+    g_inject_count = 0;
+  }
+  if (s.empty()) return false;
+  char *end = nullptr;
+  const long long k = std::strtoll(s.c_str(), &end, 10);
+  if (end == s.c_str() || k < 0) return false;
+  return g_inject_count++ == k;
+}
+}  // namespace
+
+hipError_t dev_malloc(void **p, size_t bytes) {
+  if (injected_alloc_failure()) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipMalloc(p, bytes);
+}
+
+hipError_t dev_malloc_async(void **p, size_t bytes, hipStream_t s) {
+  if (injected_alloc_failure()) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipMallocAsync(p, bytes, s);
+}
 
 int set_device_of(const hdmr_model *model) {
   int cur = -1;
@@ -63,7 +101,7 @@ struct RowKey {
 template <typename T>
 int dev_upload(T **dst, const T *src, size_t count, int64_t *bytes) {
   size_t nb = std::max<size_t>(count, 1) * sizeof(T);
-  HDMR_HIP(hipMalloc((void **)dst, nb));
+  HDMR_HIP(dev_malloc((void **)dst, nb));
   if (count) HDMR_HIP(hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice));
   *bytes += (int64_t)nb;
   return HDMR_OK;
@@ -274,7 +312,7 @@ int make_model(int32_t d, int32_t m, const double *c0, const std::vector<HostCom
   if (dsrc) {
     int64_t *dmap = nullptr;
     int64_t scratch = 0;
-    hipError_t e = hipMalloc((void **)&M->alpha, std::max<size_t>((size_t)total * ms, 1) * sizeof(double));
+    hipError_t e = dev_malloc((void **)&M->alpha, std::max<size_t>((size_t)total * ms, 1) * sizeof(double));
     if (e == hipSuccess) {
       M->device_bytes += std::max<int64_t>(total * ms, 1) * (int64_t)sizeof(double);
       rc = dev_upload(&dmap, gather.data(), gather.size(), &scratch);
@@ -287,7 +325,7 @@ int make_model(int32_t d, int32_t m, const double *c0, const std::vector<HostCom
       }
       (void)hipFree(dmap);
     } else {
-      rc = hip_fail(e, "hipMalloc(alpha)");
+      rc = hip_fail(e, "dev_malloc(alpha)");
     }
     if (rc) {
       free_device(M);
@@ -298,7 +336,7 @@ int make_model(int32_t d, int32_t m, const double *c0, const std::vector<HostCom
   {
     // FP32 surpluses for the mixed-precision path (same row order and stride)
     const int64_t count = std::max<int64_t>(total * ms, 1);
-    hipError_t e = hipMalloc((void **)&M->alpha32, (size_t)count * sizeof(float));
+    hipError_t e = dev_malloc((void **)&M->alpha32, (size_t)count * sizeof(float));
     if (e == hipSuccess) {
       M->device_bytes += count * (int64_t)sizeof(float);
       hipLaunchKernelGGL(k_to_f32, dim3((unsigned)std::min<int64_t>((count + 255) / 256, 65536)), dim3(256), 0,
