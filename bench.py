@@ -397,10 +397,14 @@ def bench_batched(args):
     dev_gb = sum(hd.hdmr_get_info(g)["device_bytes"] for g in gms) / 1e9
     log("batched: %d models, %d rows, %d points, %.1f GB of models on the device, set up in %.1f s" %
         (len(gms), rows, npts, dev_gb, setup_s))
-    hits = 0
+    hits = nz = probes = 0
     for i, (g, x, mm) in enumerate(zip(gms, X, meta)):
-        hits += hd.hdmr_eval_stats(g, x)[0] * mm["m"]
+        h_, p_ = hd.hdmr_eval_stats(g, x)
+        hits += h_ * mm["m"]
+        nz += h_
+        probes += p_
         log("work counted for %d models" % (i + 1))
+    log("nonzero basis products per point %.1f, directory lookups per point %.1f" % (nz / npts, probes / npts))
     # path and tile-shape measurement, model by model (the choices persist
     # per model and size bucket; the batched calls below reuse them)
     t0 = time.time()
@@ -425,6 +429,8 @@ def bench_batched(args):
                                "random downward-closed grids of log-uniform size 50..20000, n ~ logU(1e4, 1e6) "
                                "uniform points" % len(gms),
                    "grid_rows": rows, "points": npts, "device_GB": dev_gb, "setup_s_untimed": setup_s,
+                   "nonzeros_per_point": nz / npts, "lookups_per_point": probes / npts,
+                   "surplus_row_GBps": 8.0 * hits / t / 1e9,
                    "tuning_call_s": tune_s,
                    "paths": {str(k): int((paths == k).sum()) for k in sorted(set(paths.tolist()))}},
         "roofline": {"bound": "alu", "achieved": flops / t / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
@@ -648,12 +654,15 @@ def bench_surrogate(args):
         # per-output max-abs error on the validation points
         seg = max(1, ntr // B)
         lr, k, all_losses = 1e-3, 0, []
+        gen = torch.Generator(device="cuda:0")
+        gen.manual_seed(5)
+        # the validation target of the network: full minus order-1 interpolant
+        Rv = hd.hdmr_eval(full, Xv) - hd.hdmr_eval(o1, Xv)
         while time.perf_counter() - t0 < args.train_seconds:
-            o = np.concatenate([rng.permutation(ntr) for _ in range(seg * B // ntr + 1)])[:seg * B]
-            o = torch.from_numpy(o.astype(np.int64)).to("cuda:0")
+            o = torch.randperm(ntr, device="cuda:0", generator=gen)[:seg * B]
             all_losses.append(sg.mlp_train(net, Xtr, Ytr, o, steps=seg, batch=B, lr0=lr))
-            probe = sg.mlp_route_create(net, full, Xv, 1e-4)
-            kk, e, _ = sg.mlp_route_info(probe)
+            e = (sg.mlp_forward(net, Xv) - Rv).abs().amax(dim=0).cpu().numpy()
+            kk = int((e <= 1e-4).sum())
             k += 1
             curve.append({"segment": k, "steps": k * seg, "seconds": time.perf_counter() - t0,
                           "loss": float(all_losses[-1][-min(200, seg):].mean()), "lr0": lr,
@@ -662,6 +671,7 @@ def bench_surrogate(args):
             log("segment %d: %d steps, %.1f s, loss %.4f, validated max-abs error min %.2e median %.2e max %.2e"
                 % (k, k * seg, curve[-1]["seconds"], curve[-1]["loss"], e.min(), np.median(e), e.max()))
             lr = 1e-3 * 10.0 ** (-3.0 * min(1.0, (time.perf_counter() - t0) / args.train_seconds))
+        del Rv
         losses = np.concatenate(all_losses)
         steps = k * seg
     else:

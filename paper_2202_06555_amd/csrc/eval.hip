@@ -370,10 +370,15 @@ int check_eval_args(const hdmr_model *model, const double *points, int64_t n, co
 
 // hdmr_eval after argument checks: the gather kernel (no workspace) or the
 // cell-sorted path with its workspace allocated (ws == NULL) or supplied.
+// The environment variable HDMR_SORTED_VARIANT selects another tile shape of
+// the cell-sorted path (the variant bits of eval_sorted; diagnostics).
 int eval_any(const hdmr_model *model, const double *points, int64_t n, double *values, int precision,
              hipStream_t stream, void *ws, size_t ws_bytes, hipEvent_t *events) {
-  if (precision == HDMR_MIXED || use_sorted_path(model, n))
-    return eval_sorted(model, points, n, values, precision, stream, 0, nullptr, ws, ws_bytes, events);
+  if (precision == HDMR_MIXED || use_sorted_path(model, n)) {
+    const char *env = std::getenv("HDMR_SORTED_VARIANT");
+    const int variant = env ? (std::atoi(env) & 15) : 0;
+    return eval_sorted(model, points, n, values, precision, stream, variant, nullptr, ws, ws_bytes, events);
+  }
   const ModelView M = model->view();
   const size_t per = ((size_t)M.d * 8 + 64 * 8 + 64 * 4 + 15) & ~(size_t)15;
   const size_t smem = per * WAVES_PER_BLOCK;

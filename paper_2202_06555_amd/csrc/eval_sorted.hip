@@ -11,9 +11,10 @@
 //              and the point's key coordinates interleaved per point;
 //   sort     : radix sort of (key, point) pairs, so the points of a cell are
 //              neighbours; cell bounds;
-//   rows     : the rows of every nonempty cell through the directory
-//              (count, exclusive scan, write: a CSR of (cell, row)); work
-//              items of <= 256 points of one cell;
+//   rows     : one kernel, a wavefront per nonempty cell: the cell's rows
+//              through the directory (counted, then written to a range of
+//              the row list claimed with one atomic add) and its work items
+//              of <= 256 points (appended the same way);
 //   contract : a workgroup takes work items in turn (a grid of about one
 //              workgroup per item), stages the cell's rows and the surplus
 //              operands once per row batch, then per 64-point sub-tile reads
@@ -97,12 +98,6 @@ __global__ void k_transpose(const double *__restrict__ X, int64_t n, int d, doub
 __global__ void k_fill_u8(uint8_t *__restrict__ a, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) a[i] = 0;
 }
-__global__ void k_fill2_u32(uint32_t *__restrict__ a, uint32_t *__restrict__ b, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    a[i] = 0;
-    b[i] = 0;
-  }
-}
 
 __device__ __forceinline__ uint32_t cell_of(double x, int c) {
   const double scale = (double)(1u << c);
@@ -111,10 +106,18 @@ __device__ __forceinline__ uint32_t cell_of(double x, int c) {
 
 // Cell key of every point, and its key coordinates interleaved per point
 // (xk[p * k + q]): the contraction reads them by point id, one cache line
-// per point, with no sorted copy.
+// per point, with no sorted copy.  Also clears the pass's cell bounds
+// (nbins entries) and its two append counters (rows, work items).
 __global__ void k_keys(const double *__restrict__ XT, int64_t n, Pass P, uint16_t *__restrict__ key,
-                       int32_t *__restrict__ idx, double *__restrict__ xk) {
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+                       int32_t *__restrict__ idx, double *__restrict__ xk, uint32_t *__restrict__ bstart,
+                       uint32_t *__restrict__ bend, int nbins, uint32_t *__restrict__ counters) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, gs = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t b = g; b < nbins; b += gs) {
+    bstart[b] = 0;
+    bend[b] = 0;
+  }
+  if (g < 2) counters[g] = 0;
+  for (int64_t p = g; p < n; p += gs) {
     uint32_t kk = 0;
     for (int q = 0; q < P.k; ++q) {
       const double x = XT[(int64_t)P.dims[q] * n + p];
@@ -146,26 +149,6 @@ __global__ void k_bounds(const uint16_t *__restrict__ ks, int64_t n, uint32_t *_
   }
 }
 
-__global__ void k_tile_counts(const uint32_t *__restrict__ start, const uint32_t *__restrict__ end, int nbins,
-                              uint32_t chunk, uint32_t *__restrict__ ntile) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < nbins) ntile[b] = (end[b] - start[b] + chunk - 1) / chunk;
-}
-
-// Work items of <= chunk (<= CHUNK) consecutive sorted points of one cell:
-// (first sorted point, count, rows of the cell, first CSR entry of the cell).
-__global__ void k_write_tiles(const uint32_t *__restrict__ start, const uint32_t *__restrict__ end,
-                              const uint32_t *__restrict__ ntile, const uint32_t *__restrict__ toff,
-                              const uint32_t *__restrict__ crows, const uint32_t *__restrict__ coff, int nbins,
-                              uint32_t chunk, uint4 *__restrict__ tiles, uint32_t *__restrict__ ntiles) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nbins) return;
-  const uint32_t s0 = start[b], cnt = end[b] - start[b];
-  for (uint32_t t = 0; t < ntile[b]; ++t)
-    tiles[toff[b] + t] = make_uint4(s0 + t * chunk, min(cnt - t * chunk, chunk), crows[b], coff[b]);
-  if (b == nbins - 1) *ntiles = toff[b] + ntile[b];
-}
-
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -182,102 +165,145 @@ struct alignas(16) CellRow {
   uint32_t pad3[2];
 };
 
-// Discovery of the rows of every nonempty cell of a pass: one wavefront per
-// cell, lanes over the pass's level multi-indices (one candidate basis
-// function per level multi-index, 2^(l-c-1) per dimension where the level l
-// is finer than the cell level c), directory lookup, ballot + prefix
-// compaction.  Count mode (off == NULL): nrows[cell] = number of rows (0 for
-// empty cells).  Write mode: row r of the cell goes to list[off[cell] + r],
-// its odd indices to idx[off[cell] + r].
-__global__ __launch_bounds__(256) void k_cell_rows(ModelView M, Pass P, const PassTup *__restrict__ ptups,
-                                                   const uint32_t *__restrict__ bstart,
-                                                   const uint32_t *__restrict__ bend, int nbins,
-                                                   const uint32_t *__restrict__ off, CellRow *__restrict__ list,
-                                                   uint4 *__restrict__ idx, uint32_t *__restrict__ nrows_out) {
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int64_t nw = (int64_t)gridDim.x * WAVES_PER_BLOCK;
-  for (int64_t bin = (int64_t)blockIdx.x * WAVES_PER_BLOCK + threadIdx.x / WAVE; bin < nbins; bin += nw) {
-    if (bend[bin] <= bstart[bin]) {
-      if (!off && lane == 0) nrows_out[bin] = 0;
-      continue;
+// The rows of one cell of a pass, for a whole wavefront: lanes over the
+// pass's level multi-indices (one candidate basis function per level
+// multi-index, 2^(l-c-1) per dimension where the level l is finer than the
+// cell level c), directory lookup, ballot + prefix compaction.  Returns the
+// number of rows; with list != NULL, row r goes to list[base + r] and its
+// odd indices to idx[base + r].
+__device__ int cell_rows(const ModelView &M, const Pass &P, const PassTup *__restrict__ ptups, uint32_t key,
+                         uint32_t base, CellRow *__restrict__ list, uint4 *__restrict__ idx, int lane) {
+  uint32_t cellq[KMAX];
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) cellq[q] = q < P.k ? (key >> P.shift[q]) & ((1u << P.cell_lv[q]) - 1u) : 0u;
+  const bool write = list != nullptr;
+  int nrows = 0;
+  for (int b0 = P.tup_begin; b0 < P.tup_end; b0 += WAVE) {
+    const int j = b0 + lane;
+    TupDesc T{};
+    PassTup PT{};
+    uint32_t lo[KMAX] = {0, 0, 0, 0}, cnt[KMAX] = {1, 1, 1, 1}, ncand = 0;
+    if (j < P.tup_end) {
+      PT = ptups[j];
+      T = M.tups[PT.tup];
+      ncand = 1;
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q) {
+        if (q < T.k) {
+          const int c = P.cell_lv[PT.pos[q]], l = T.lv[q];
+          const uint32_t cell = cellq[PT.pos[q]];
+          if (l <= c) {
+            lo[q] = (cell >> (c - l)) >> 1;
+            cnt[q] = 1;
+          } else {
+            lo[q] = (cell << (l - c)) >> 1;
+            cnt[q] = 1u << (l - c - 1);
+          }
+          ncand *= cnt[q];
+        }
+      }
     }
-    const uint32_t base = off ? off[bin] : 0u;
-    const uint32_t key = (uint32_t)bin;
-    uint32_t cellq[KMAX];
+    uint32_t maxc = ncand;
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q) cellq[q] = q < P.k ? (key >> P.shift[q]) & ((1u << P.cell_lv[q]) - 1u) : 0u;
-    int nrows = 0;
-    for (int b0 = P.tup_begin; b0 < P.tup_end; b0 += WAVE) {
-      const int j = b0 + lane;
-      TupDesc T{};
-      PassTup PT{};
-      uint32_t lo[KMAX] = {0, 0, 0, 0}, cnt[KMAX] = {1, 1, 1, 1}, ncand = 0;
-      if (j < P.tup_end) {
-        PT = ptups[j];
-        T = M.tups[PT.tup];
-        ncand = 1;
+    for (int off = 1; off < WAVE; off <<= 1) maxc = max(maxc, (uint32_t)__shfl_xor((int)maxc, off, WAVE));
+    for (uint32_t cand = 0; cand < maxc; ++cand) {
+      int32_t row = -1;
+      uint32_t half[KMAX] = {0, 0, 0, 0};
+      if (cand < ncand) {
+        uint32_t rem = cand, slot = 0;
 #pragma unroll
-        for (int q = 0; q < KMAX; ++q) {
+        for (int q = KMAX - 1; q >= 0; --q)
           if (q < T.k) {
-            const int c = P.cell_lv[PT.pos[q]], l = T.lv[q];
-            const uint32_t cell = cellq[PT.pos[q]];
-            if (l <= c) {
-              lo[q] = (cell >> (c - l)) >> 1;
-              cnt[q] = 1;
-            } else {
-              lo[q] = (cell << (l - c)) >> 1;
-              cnt[q] = 1u << (l - c - 1);
-            }
-            ncand *= cnt[q];
+            half[q] = lo[q] + rem % cnt[q];
+            rem /= cnt[q];
           }
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q)
+          if (q < T.k) slot = (slot << (T.lv[q] - 1)) | half[q];
+        row = lookup_row(T, slot, M.tab);
+      }
+      const bool hit = row >= 0;
+      const uint64_t mask = ballot(hit);
+      if (hit && write) {
+        const uint32_t e = base + (uint32_t)(nrows + lanes_below(mask));
+        {
+          CellRow R{};
+          R.row = row;
+          R.w = T.w;
+          R.k = T.k;
+          uint4 ix;
+#pragma unroll
+          for (int q = 0; q < KMAX; ++q) {
+            R.pos[q] = PT.pos[q];
+            R.lv[q] = T.lv[q];
+          }
+          ix.x = 2u * half[0] + 1u;
+          ix.y = 2u * half[1] + 1u;
+          ix.z = 2u * half[2] + 1u;
+          ix.w = 2u * half[3] + 1u;
+          list[e] = R;
+          idx[e] = ix;
         }
       }
-      uint32_t maxc = ncand;
-#pragma unroll
-      for (int off = 1; off < WAVE; off <<= 1) maxc = max(maxc, (uint32_t)__shfl_xor((int)maxc, off, WAVE));
-      for (uint32_t cand = 0; cand < maxc; ++cand) {
-        int32_t row = -1;
-        uint32_t half[KMAX] = {0, 0, 0, 0};
-        if (cand < ncand) {
-          uint32_t rem = cand, slot = 0;
-#pragma unroll
-          for (int q = KMAX - 1; q >= 0; --q)
-            if (q < T.k) {
-              half[q] = lo[q] + rem % cnt[q];
-              rem /= cnt[q];
-            }
-#pragma unroll
-          for (int q = 0; q < KMAX; ++q)
-            if (q < T.k) slot = (slot << (T.lv[q] - 1)) | half[q];
-          row = lookup_row(T, slot, M.tab);
-        }
-        const bool hit = row >= 0;
-        const uint64_t mask = ballot(hit);
-        if (hit && off) {
-          const uint32_t e = base + (uint32_t)(nrows + lanes_below(mask));
-          {
-            CellRow R{};
-            R.row = row;
-            R.w = T.w;
-            R.k = T.k;
-            uint4 ix;
-#pragma unroll
-            for (int q = 0; q < KMAX; ++q) {
-              R.pos[q] = PT.pos[q];
-              R.lv[q] = T.lv[q];
-            }
-            ix.x = 2u * half[0] + 1u;
-            ix.y = 2u * half[1] + 1u;
-            ix.z = 2u * half[2] + 1u;
-            ix.w = 2u * half[3] + 1u;
-            list[e] = R;
-            idx[e] = ix;
-          }
-        }
-        nrows += __popcll(mask);
-      }
+      nrows += __popcll(mask);
     }
-    if (!off && lane == 0) nrows_out[bin] = (uint32_t)nrows;
+  }
+  return nrows;
+}
+
+// Rows and work items of every nonempty cell of a pass.  A workgroup takes
+// SETUP_CELLS consecutive cells (each wave SETUP_CELLS / 4 of them): it counts
+// every cell's rows, claims one range of the row list and one of the
+// work-item list for all its cells with one atomic add each (counters[0],
+// counters[1]; the latter ends as the number of items), then writes the rows
+// and the items (first sorted point, count <= chunk, rows of the cell, first
+// row entry).  The order of the workgroups' ranges in the lists depends on
+// scheduling; no point's result does (a point's sums run over its own cell's
+// rows in their directory order).
+constexpr int SETUP_CELLS = 16;
+__global__ __launch_bounds__(256) void k_cell_setup(ModelView M, Pass P, const PassTup *__restrict__ ptups,
+                                                    const uint32_t *__restrict__ bstart,
+                                                    const uint32_t *__restrict__ bend, int nbins, uint32_t chunk,
+                                                    CellRow *__restrict__ list, uint4 *__restrict__ idx,
+                                                    uint4 *__restrict__ tiles, uint32_t *__restrict__ counters) {
+  __shared__ uint32_t s_nr[SETUP_CELLS], s_nt[SETUP_CELLS], s_ro[SETUP_CELLS], s_to[SETUP_CELLS], s_base[2];
+  const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+  constexpr int PER_WAVE = SETUP_CELLS / WAVES_PER_BLOCK;
+  const int64_t c0 = (int64_t)blockIdx.x * SETUP_CELLS;
+  for (int c = wid * PER_WAVE; c < (wid + 1) * PER_WAVE; ++c) {
+    const int64_t bin = c0 + c;
+    uint32_t nr = 0, nt = 0;
+    if (bin < nbins && bend[bin] > bstart[bin]) {
+      nr = (uint32_t)cell_rows(M, P, ptups, (uint32_t)bin, 0u, nullptr, nullptr, lane);
+      nt = (bend[bin] - bstart[bin] + chunk - 1) / chunk;
+    }
+    if (lane == 0) {
+      s_nr[c] = nr;
+      s_nt[c] = nt;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t r = 0, q = 0;
+    for (int c = 0; c < SETUP_CELLS; ++c) {
+      s_ro[c] = r;
+      s_to[c] = q;
+      r += s_nr[c];
+      q += s_nt[c];
+    }
+    s_base[0] = r ? atomicAdd(&counters[0], r) : 0u;
+    s_base[1] = q ? atomicAdd(&counters[1], q) : 0u;
+  }
+  __syncthreads();
+  for (int c = wid * PER_WAVE; c < (wid + 1) * PER_WAVE; ++c)
+    if (s_nr[c]) cell_rows(M, P, ptups, (uint32_t)(c0 + c), s_base[0] + s_ro[c], list, idx, lane);
+  for (int c = 0; c < SETUP_CELLS; ++c) {
+    const int64_t bin = c0 + c;
+    for (uint32_t q = threadIdx.x; q < s_nt[c]; q += blockDim.x) {
+      const uint32_t s0 = bstart[bin], cnt = bend[bin] - s0;
+      tiles[s_base[1] + s_to[c] + q] = make_uint4(s0 + q * chunk, min(cnt - q * chunk, chunk), s_nr[c],
+                                                  s_base[0] + s_ro[c]);
+    }
   }
 }
 
@@ -993,7 +1019,7 @@ struct PassBufs {
   uint16_t *key, *key_s;
   int32_t *idx, *spid;
   double *xk;
-  uint32_t *bstart, *bend, *ntile, *toff, *ntiles, *crows, *coff;
+  uint32_t *bstart, *bend, *counters;  // counters: rows appended, work items appended
   CellRow *clist;
   uint4 *cidx, *tiles;
   void *tmp;
@@ -1022,11 +1048,7 @@ void carve_workspace(Carve &C, Workspace &W, int64_t n, int d, int AS, bool mixe
     B.xk = C.take<double>((size_t)n * KMAX);
     B.bstart = C.take<uint32_t>(65536);
     B.bend = C.take<uint32_t>(65536);
-    B.ntile = C.take<uint32_t>(65536);
-    B.toff = C.take<uint32_t>(65536);
-    B.ntiles = C.take<uint32_t>(1);
-    B.crows = C.take<uint32_t>(65536);
-    B.coff = C.take<uint32_t>(65536);
+    B.counters = C.take<uint32_t>(2);
     B.clist = C.take<CellRow>((size_t)list_max);
     B.cidx = C.take<uint4>((size_t)list_max);
     B.tiles = C.take<uint4>(max_tiles);
@@ -1056,16 +1078,14 @@ int eval_sorted_workspace(const hdmr_model *model, int64_t n, int precision, siz
   const int AS = (model->m + 15) & ~15;
   int64_t list_max = 1;
   for (const Pass &P : model->passes) list_max = std::max<int64_t>(list_max, P.list_bound);
-  size_t tmp_sort = 0, tmp_scan = 0;
+  size_t tmp_sort = 0;
   if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_sort, (uint16_t *)nullptr, (uint16_t *)nullptr,
                                          (int32_t *)nullptr, (int32_t *)nullptr, (int)std::max<int64_t>(n, 1), 0, 16,
-                                         (hipStream_t)0) != hipSuccess ||
-      hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_scan, (uint32_t *)nullptr, (uint32_t *)nullptr, 65536,
-                                       (hipStream_t)0) != hipSuccess)
+                                         (hipStream_t)0) != hipSuccess)
     return fail(HDMR_EDEVICE, "hipcub temporary storage query failed");
   Carve C;
   Workspace W{};
-  carve_workspace(C, W, n, model->d, AS, precision == HDMR_MIXED, list_max, std::max(tmp_sort, tmp_scan));
+  carve_workspace(C, W, n, model->d, AS, precision == HDMR_MIXED, list_max, tmp_sort);
   *bytes = C.off + 256;
   return HDMR_OK;
 }
@@ -1130,13 +1150,10 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
   int64_t list_max = 1;
   for (const Pass &P : model->passes) list_max = std::max<int64_t>(list_max, P.list_bound);
   if (list_max >= (int64_t)UINT32_MAX) return fail(HDMR_EUNSUPPORTED, "cell row lists exceed 2^32 entries");
-  size_t tmp_sort = 0, tmp_scan = 0;
-  if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_sort, (uint16_t *)nullptr, (uint16_t *)nullptr,
-                                         (int32_t *)nullptr, (int32_t *)nullptr, (int)n, 0, 16, stream) != hipSuccess ||
-      hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_scan, (uint32_t *)nullptr, (uint32_t *)nullptr, 65536,
-                                       stream) != hipSuccess)
+  size_t tmp_bytes = 0;
+  if (hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, (uint16_t *)nullptr, (uint16_t *)nullptr,
+                                         (int32_t *)nullptr, (int32_t *)nullptr, (int)n, 0, 16, stream) != hipSuccess)
     return fail(HDMR_EDEVICE, "hipcub temporary storage query failed");
-  const size_t tmp_bytes = std::max(tmp_sort, tmp_scan);
   Carve C;
   Workspace W{};
   carve_workspace(C, W, n, d, AS, mixed, list_max, tmp_bytes);
@@ -1175,13 +1192,15 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
   // points of one cell), within [1024, TILE_GRID]; each walks the items
   // with a stride of the grid
   // tile shape (variant bits): 1 = the smaller row batch, 2 = work items of
-  // CHUNK / 2 points, 4 = a persistent grid of 3 workgroups per CU
+  // CHUNK / 2 points, 4 = a persistent grid of 3 workgroups per CU, 8 = one
+  // of 2 workgroups per CU (leaves each CU room for the second stream's
+  // kernels while the contraction runs)
   const uint32_t chunk = (variant & 2) ? CHUNK / 2 : CHUNK;
   unsigned tgrid = (unsigned)std::max<int64_t>(1024, std::min<int64_t>((n + chunk - 1) / chunk, TILE_GRID));
-  if (variant & 4) {
+  if (variant & 12) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, model->device) == hipSuccess && cus > 0)
-      tgrid = (unsigned)(3 * cus);
+      tgrid = (unsigned)(((variant & 4) ? 3 : 2) * cus);
   }
   const unsigned ga = (unsigned)std::min<int64_t>((n * AS + 255) / 256, 65536);
   if (e == hipSuccess) {
@@ -1201,36 +1220,24 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
     const int bsel = (int)(pi % NBUF);
     PassBufs &B = W.pb[bsel];
     const int nbins = 1 << P.key_bits;
-    const unsigned gb = (unsigned)((nbins + 255) / 256);
-    const unsigned gc = (unsigned)std::min((nbins + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, 8192);
+    const unsigned gc = (unsigned)((nbins + SETUP_CELLS - 1) / SETUP_CELLS);
     // keys, sort and row discovery of this pass on the second stream, once
     // the contraction NBUF passes back is done with this buffer set
     if (pi >= NBUF && (e = hipStreamWaitEvent(side, ev_done[bsel], 0)) != hipSuccess) break;
     {
       StageTimer tm(STAGE_SORT, side);
-      hipLaunchKernelGGL(k_keys, dim3(gs), dim3(256), 0, side, W.xt, n, P, B.key, B.idx, B.xk);
+      hipLaunchKernelGGL(k_keys, dim3(gs), dim3(256), 0, side, W.xt, n, P, B.key, B.idx, B.xk, B.bstart, B.bend,
+                         nbins, B.counters);
       size_t tb = tmp_bytes;
       e = hipcub::DeviceRadixSort::SortPairs(B.tmp, tb, B.key, B.key_s, B.idx, B.spid, (int)n, 0, P.key_bits, side);
       if (e != hipSuccess) break;
-      hipLaunchKernelGGL(k_fill2_u32, dim3(gb), dim3(256), 0, side, B.bstart, B.bend, (int64_t)nbins);
       hipLaunchKernelGGL(k_bounds, dim3(gs), dim3(256), 0, side, B.key_s, n, B.bstart, B.bend);
     }
     {
-      // rows of every nonempty cell (count, offsets, write), then the tiles
+      // rows and work items of every nonempty cell
       StageTimer tm(STAGE_ROWS, side);
-      hipLaunchKernelGGL(k_cell_rows, dim3(gc), dim3(256), 0, side, M, P, model->pass_tups, B.bstart, B.bend, nbins,
-                         (const uint32_t *)nullptr, B.clist, B.cidx, B.crows);
-      size_t tb = tmp_bytes;
-      e = hipcub::DeviceScan::ExclusiveSum(B.tmp, tb, B.crows, B.coff, nbins, side);
-      if (e != hipSuccess) break;
-      hipLaunchKernelGGL(k_cell_rows, dim3(gc), dim3(256), 0, side, M, P, model->pass_tups, B.bstart, B.bend, nbins,
-                         (const uint32_t *)B.coff, B.clist, B.cidx, B.crows);
-      hipLaunchKernelGGL(k_tile_counts, dim3(gb), dim3(256), 0, side, B.bstart, B.bend, nbins, chunk, B.ntile);
-      tb = tmp_bytes;
-      e = hipcub::DeviceScan::ExclusiveSum(B.tmp, tb, B.ntile, B.toff, nbins, side);
-      if (e != hipSuccess) break;
-      hipLaunchKernelGGL(k_write_tiles, dim3(gb), dim3(256), 0, side, B.bstart, B.bend, B.ntile, B.toff, B.crows,
-                         B.coff, nbins, chunk, B.tiles, B.ntiles);
+      hipLaunchKernelGGL(k_cell_setup, dim3(gc), dim3(256), 0, side, M, P, model->pass_tups, B.bstart, B.bend, nbins,
+                         chunk, B.clist, B.cidx, B.tiles, B.counters);
     }
     if ((e = hipEventRecord(ev_sorted[bsel], side)) != hipSuccess) break;
     if ((e = hipStreamWaitEvent(stream, ev_sorted[bsel], 0)) != hipSuccess) break;
@@ -1240,31 +1247,31 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
       for (int o0 = 0; o0 < AS; o0 += 64) {
         if (G && narrow)
           hipLaunchKernelGGL((k_tile_fp64<TR_GRAD, true, true>), dim3(tgrid), dim3(256), 0, stream, M, P, B.tiles,
-                             B.ntiles, B.clist, B.cidx, B.spid, B.xk, n, W.acc, AS, o0, G);
+                             B.counters + 1, B.clist, B.cidx, B.spid, B.xk, n, W.acc, AS, o0, G);
         else if (G)
           hipLaunchKernelGGL((k_tile_fp64<TR_GRAD, true, false>), dim3(tgrid), dim3(256), 0, stream, M, P, B.tiles,
-                             B.ntiles, B.clist, B.cidx, B.spid, B.xk, n, W.acc, AS, o0, G);
+                             B.counters + 1, B.clist, B.cidx, B.spid, B.xk, n, W.acc, AS, o0, G);
         else if (!mixed && !(variant & 1) && narrow)
           hipLaunchKernelGGL((k_tile_fp64<TR_FP64, false, true>), dim3(tgrid), dim3(256), 0, stream, M, P, B.tiles,
-                             B.ntiles, B.clist, B.cidx, B.spid, B.xk, n, W.acc, AS, o0, (double *)nullptr);
+                             B.counters + 1, B.clist, B.cidx, B.spid, B.xk, n, W.acc, AS, o0, (double *)nullptr);
         else if (!mixed && !(variant & 1))
           hipLaunchKernelGGL((k_tile_fp64<TR_FP64, false, false>), dim3(tgrid), dim3(256), 0, stream, M, P, B.tiles,
-                             B.ntiles, B.clist, B.cidx, B.spid, B.xk, n, W.acc, AS, o0, (double *)nullptr);
+                             B.counters + 1, B.clist, B.cidx, B.spid, B.xk, n, W.acc, AS, o0, (double *)nullptr);
         else if (!mixed && narrow)
           hipLaunchKernelGGL((k_tile_fp64<TR_FP64_ALT, false, true>), dim3(tgrid), dim3(256), 0, stream, M, P,
-                             B.tiles, B.ntiles, B.clist, B.cidx, B.spid, B.xk, n, W.acc, AS, o0, (double *)nullptr);
+                             B.tiles, B.counters + 1, B.clist, B.cidx, B.spid, B.xk, n, W.acc, AS, o0, (double *)nullptr);
         else if (!mixed)
           hipLaunchKernelGGL((k_tile_fp64<TR_FP64_ALT, false, false>), dim3(tgrid), dim3(256), 0, stream, M, P,
-                             B.tiles, B.ntiles, B.clist, B.cidx, B.spid, B.xk, n, W.acc, AS, o0, (double *)nullptr);
+                             B.tiles, B.counters + 1, B.clist, B.cidx, B.spid, B.xk, n, W.acc, AS, o0, (double *)nullptr);
         else if (split2)
-          hipLaunchKernelGGL((k_tile_mixed<TR_MIXED, 2>), dim3(tgrid), dim3(256), 0, stream, M, P, B.tiles, B.ntiles,
+          hipLaunchKernelGGL((k_tile_mixed<TR_MIXED, 2>), dim3(tgrid), dim3(256), 0, stream, M, P, B.tiles, B.counters + 1,
                              B.clist, B.cidx, B.spid, B.xk, (const float *)model->alpha32, n, W.acc32, AS, o0);
         else if (!(variant & 1))
-          hipLaunchKernelGGL((k_tile_mixed<TR_MIXED, 3>), dim3(tgrid), dim3(256), 0, stream, M, P, B.tiles, B.ntiles,
+          hipLaunchKernelGGL((k_tile_mixed<TR_MIXED, 3>), dim3(tgrid), dim3(256), 0, stream, M, P, B.tiles, B.counters + 1,
                              B.clist, B.cidx, B.spid, B.xk, (const float *)model->alpha32, n, W.acc32, AS, o0);
         else
           hipLaunchKernelGGL((k_tile_mixed<TR_MIXED_ALT, 3>), dim3(tgrid), dim3(256), 0, stream, M, P, B.tiles,
-                             B.ntiles, B.clist, B.cidx, B.spid, B.xk, (const float *)model->alpha32, n, W.acc32, AS,
+                             B.counters + 1, B.clist, B.cidx, B.spid, B.xk, (const float *)model->alpha32, n, W.acc32, AS,
                              o0);
       }
     }

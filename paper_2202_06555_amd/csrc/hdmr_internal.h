@@ -165,7 +165,8 @@ void keep_pool_memory(int device);
 // Cell-sorted evaluation (eval_sorted.hip), precision HDMR_PLAIN_FP64 or
 // HDMR_MIXED; variant selects the contraction's tile shape (bit 0: the
 // smaller row batch; bit 1: work items of half the points; bit 2: a
-// persistent grid of three workgroups per CU), 0 is the default.  With G (n x d x m, plain precision only) the
+// persistent grid of three workgroups per CU; bit 3: one of two per CU), 0
+// is the default.  With G (n x d x m, plain precision only) the
 // gradient is computed as well.
 // ws_base (device, ws_bytes bytes) supplies the workspace; with NULL it is
 // allocated stream-ordered on the device's pool and released at the end.
