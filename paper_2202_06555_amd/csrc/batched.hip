@@ -57,7 +57,10 @@ __global__ void k_zero_u64(unsigned long long *c) {
 // directory lookup), compacts the hits with ballot + prefix into LDS and
 // contracts them with lanes over outputs (eq (3.6)); c0 + sum is written
 // (eq (3.16)).  Every wave leaves once the queue counter passes the last unit.
-__global__ __launch_bounds__(256) void k_eval_batched(const BatchItem *__restrict__ items, int nitems,
+// NOPL: the largest outputs-per-lane count of the launch's items (1: every
+// model has m <= 64, and the kernel keeps one accumulator per lane).
+template <int NOPL>
+__global__ __launch_bounds__(256, NOPL == 1 ? 5 : 4) void k_eval_batched(const BatchItem *__restrict__ items, int nitems,
                                                       int64_t total_units, unsigned long long *__restrict__ counter,
                                                       int dmax) {
   extern __shared__ __align__(16) char smem[];
@@ -94,32 +97,23 @@ __global__ __launch_bounds__(256) void k_eval_batched(const BatchItem *__restric
       }
       wave_sync();
       const bool is_nan = ballot(nan_here) != 0;
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
-      // the level multi-index descriptors do not depend on the point: the
-      // next group's are loaded while the current group is processed
-      TupDesc Tn{};
-      if (lane < M.ntup) Tn = M.tups[lane];
-      for (int t0 = 0; t0 < M.ntup; t0 += WAVE) {
-        const int t = t0 + lane;
-        const TupDesc T = Tn;
-        if (t + WAVE < M.ntup) Tn = M.tups[t + WAVE];
-        int32_t row = -1;
-        double w = 0.0;
-        if (t < M.ntup) {
-          w = T.w;
-          uint32_t slot = 0;
+      double acc[NOPL];
 #pragma unroll
-          for (int q = 0; q < KMAX; ++q) {
-            if (q < T.k) {
-              uint32_t half, c;
-              double phi, tt;
-              active_cell(xs[T.dims[q]], T.lv[q], half, phi, tt, c);
-              w *= phi;
-              slot = (slot << (T.lv[q] - 1)) | half;
-            }
-          }
-          if (w != 0.0) row = lookup_row(T, slot, M.tab);
-        }
+      for (int j = 0; j < NOPL; ++j) acc[j] = 0.0;
+      // Software pipeline over groups of 64 level multi-indices: the
+      // directory lookups of group g + 1 are issued before the surplus rows
+      // of group g's hits are loaded, so both sets of loads are in flight
+      // together; the descriptors run one group further ahead.
+      TupDesc Tn{};
+      if (WAVE + lane < M.ntup) Tn = M.tups[WAVE + lane];
+      int32_t row = -1;
+      double w = 0.0;
+      {
+        TupDesc T{};
+        if (lane < M.ntup) T = M.tups[lane];
+        group_lookup(M, xs, lane, T, row, w);
+      }
+      for (int t0 = 0; t0 < M.ntup; t0 += WAVE) {
         const bool hit = row >= 0;
         const uint64_t mask = ballot(hit);
         const int cnt = __popcll(mask);
@@ -129,41 +123,53 @@ __global__ __launch_bounds__(256) void k_eval_batched(const BatchItem *__restric
           qw[pos] = w;
         }
         wave_sync();
-        int h = sub;
-        if (opl == 1) {
-          // four hits in flight per step
+        row = -1;
+        w = 0.0;
+        if (t0 + WAVE < M.ntup) {
+          const TupDesc T = Tn;
+          if (t0 + 2 * WAVE + lane < M.ntup) Tn = M.tups[t0 + 2 * WAVE + lane];
+          group_lookup(M, xs, t0 + WAVE + lane < M.ntup ? lane : -1, T, row, w);
+        }
+        if (NOPL == 1 || opl == 1) {
+          // up to HF hits per step, all their row loads in flight together;
+          // each lane adds its hits in queue order
+          constexpr int HF = 8;
           const bool on = ol < m;
-          for (; h + 3 * HPI < cnt; h += 4 * HPI) {
-            int32_t r[4];
-            double ww[4], a[4];
+          for (int h = sub; h < cnt; h += HF * HPI) {
+            int32_t r[HF];
+            double ww[HF], a[HF];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              r[u] = qrow[h + u * HPI];
-              ww[u] = qw[h + u * HPI];
+            for (int u = 0; u < HF; ++u) {
+              const int e = h + u * HPI;
+              const int ec = e < cnt ? e : 0;
+              r[u] = qrow[ec];
+              ww[u] = qw[ec];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) a[u] = on ? M.alpha[(int64_t)r[u] * M.ms + ol] : 0.0;
+            for (int u = 0; u < HF; ++u) a[u] = on ? M.alpha[(int64_t)r[u] * M.ms + ol] : 0.0;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc[0] = fma(ww[u], a[u], acc[0]);
+            for (int u = 0; u < HF; ++u)
+              if (h + u * HPI < cnt) acc[0] = fma(ww[u], a[u], acc[0]);
           }
-        }
-        for (; h < cnt; h += HPI) {
-          const int32_t r = qrow[h];
-          const double ww = qw[h];
+        } else {
+          for (int h = sub; h < cnt; h += HPI) {
+            const int32_t r = qrow[h];
+            const double ww = qw[h];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int o = ol + j * WAVE;
-            if (j < opl && o < m) acc[j] = fma(ww, M.alpha[(int64_t)r * M.ms + o], acc[j]);
+            for (int j = 0; j < NOPL; ++j) {
+              const int o = ol + j * WAVE;
+              if (j < opl && o < m) acc[j] = fma(ww, M.alpha[(int64_t)r * M.ms + o], acc[j]);
+            }
           }
         }
         wave_sync();
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < NOPL; ++j)
         for (int off = OW; off < WAVE; off <<= 1) acc[j] += __shfl_xor(acc[j], off, WAVE);
       if (sub == 0) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NOPL; ++j) {
           const int o = ol + j * WAVE;
           if (j < opl && o < m) I.Y[p * m + o] = is_nan ? __builtin_nan("") : M.c0[o] + acc[j];
         }
@@ -247,19 +253,27 @@ double cost_per_point(const hdmr_model *mdl) {
 }
 
 // Launch the persistent kernel for the given items (already in device memory).
+// maxopl: the largest outputs-per-lane count of the items.
 int launch_persistent(const BatchItem *d_items, int nitems, int64_t total_units, unsigned long long *counter, int dmax,
-                      hipStream_t s) {
+                      int maxopl, hipStream_t s) {
   const size_t per = ((size_t)dmax * 8 + 64 * 8 + 64 * 4 + 15) & ~(size_t)15;
   const size_t smem = per * WAVES_PER_BLOCK;
   int dev = 0, cus = 0, per_cu = 0;
   HDMR_HIP(hipGetDevice(&dev));
   HDMR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  HDMR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_eval_batched, WAVE * WAVES_PER_BLOCK, smem));
+  const bool narrow = maxopl <= 1;
+  HDMR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, narrow ? reinterpret_cast<const void *>(k_eval_batched<1>) : reinterpret_cast<const void *>(k_eval_batched<4>),
+      WAVE * WAVES_PER_BLOCK, smem));
   const int64_t want = (total_units + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
   const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * std::max(per_cu, 1), want));
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, counter);
-  hipLaunchKernelGGL(k_eval_batched, dim3(blocks), dim3(WAVE * WAVES_PER_BLOCK), smem, s, d_items, nitems,
-                     total_units, counter, dmax);
+  if (narrow)
+    hipLaunchKernelGGL(k_eval_batched<1>, dim3(blocks), dim3(WAVE * WAVES_PER_BLOCK), smem, s, d_items, nitems,
+                       total_units, counter, dmax);
+  else
+    hipLaunchKernelGGL(k_eval_batched<4>, dim3(blocks), dim3(WAVE * WAVES_PER_BLOCK), smem, s, d_items, nitems,
+                       total_units, counter, dmax);
   HDMR_HIP(hipGetLastError());
   return HDMR_OK;
 }
@@ -275,7 +289,7 @@ int gather_single(const hdmr_model *mdl, const double *X, double *Y, int64_t n, 
   HDMR_HIP(dev_malloc_async((void **)&d_item, sizeof(BatchItem), s));
   HDMR_HIP(dev_malloc_async((void **)&counter, sizeof(unsigned long long), s));
   HDMR_HIP(hipMemcpyAsync(d_item, &I, sizeof(BatchItem), hipMemcpyHostToDevice, s));
-  int rc = launch_persistent(d_item, 1, units, counter, mdl->d, s);
+  int rc = launch_persistent(d_item, 1, units, counter, mdl->d, I.opl, s);
   (void)hipFreeAsync(d_item, s);
   (void)hipFreeAsync(counter, s);
   // the host copy of the item must outlive the asynchronous upload
@@ -445,8 +459,10 @@ extern "C" int hdmr_eval_batched(const hdmr_model *const *models, const double *
       E.key = key;
       std::vector<BatchItem> host;
       int64_t units = 0;
+      int maxopl = 1;
       for (int32_t i : gi) {
         BatchItem I = make_item(models[i], points[i], values[i], n[i]);
+        maxopl = std::max(maxopl, (int)I.opl);
         I.unit_begin = units;
         units += (n[i] + UNIT_POINTS - 1) / UNIT_POINTS;
         host.push_back(I);
@@ -464,7 +480,7 @@ extern "C" int hdmr_eval_batched(const hdmr_model *const *models, const double *
       }
       if (e == hipSuccess) e = hipStreamBeginCapture(g_capture, hipStreamCaptureModeThreadLocal);
       if (e == hipSuccess) {
-        rc = launch_persistent(E.items, (int)host.size(), units, E.counter, dmax, g_capture);
+        rc = launch_persistent(E.items, (int)host.size(), units, E.counter, dmax, maxopl, g_capture);
         hipGraph_t g = nullptr;
         const hipError_t e2 = hipStreamEndCapture(g_capture, &g);
         E.graph = g;

@@ -69,32 +69,19 @@ __global__ __launch_bounds__(256) void k_eval_fp64(ModelView M, const double *__
     double acc[OPL];
 #pragma unroll
     for (int j = 0; j < OPL; ++j) acc[j] = 0.0;
-    // the descriptors do not depend on the point: the next group's are loaded
-    // while the current group is processed
+    // software pipeline over groups of 64 level multi-indices: the directory
+    // lookups of group g + 1 are issued before the surplus rows of group g's
+    // hits are loaded; the descriptors run one group further ahead
     TupDesc Tn{};
-    if (lane < M.ntup) Tn = M.tups[lane];
+    if (WAVE + lane < M.ntup) Tn = M.tups[WAVE + lane];
+    int32_t row = -1;
+    double w = 0.0;
+    {
+      TupDesc T{};
+      if (lane < M.ntup) T = M.tups[lane];
+      group_lookup(M, L.xs, lane, T, row, w);
+    }
     for (int t0 = 0; t0 < M.ntup; t0 += WAVE) {
-      // ---- lookup: one tuple per lane ----
-      const int t = t0 + lane;
-      const TupDesc T = Tn;
-      if (t + WAVE < M.ntup) Tn = M.tups[t + WAVE];
-      int32_t row = -1;
-      double w = 0.0;
-      if (t < M.ntup) {
-        w = T.w;
-        uint32_t slot = 0;
-#pragma unroll
-        for (int q = 0; q < KMAX; ++q) {
-          if (q < T.k) {
-            uint32_t half, c;
-            double phi, tt;
-            active_cell(L.xs[T.dims[q]], T.lv[q], half, phi, tt, c);
-            w *= phi;
-            slot = (slot << (T.lv[q] - 1)) | half;
-          }
-        }
-        if (w != 0.0) row = lookup_row(T, slot, M.tab);
-      }
       // ---- compact hits (ballot + prefix) ----
       const bool hit = row >= 0;
       const uint64_t mask = ballot(hit);
@@ -105,35 +92,38 @@ __global__ __launch_bounds__(256) void k_eval_fp64(ModelView M, const double *__
         L.qw[pos] = w;
       }
       wave_sync();
-      // ---- contract: lanes over outputs ----
-      int h = sub;
-      for (; h + 3 * HPI < cnt; h += 4 * HPI) {
-        int32_t r[4];
-        double ww[4];
+      // ---- next group's lookups ----
+      row = -1;
+      w = 0.0;
+      if (t0 + WAVE < M.ntup) {
+        const TupDesc T = Tn;
+        if (t0 + 2 * WAVE + lane < M.ntup) Tn = M.tups[t0 + 2 * WAVE + lane];
+        group_lookup(M, L.xs, t0 + WAVE + lane < M.ntup ? lane : -1, T, row, w);
+      }
+      // ---- contract: lanes over outputs, up to HF hits per step with all
+      // their row loads in flight; each lane adds its hits in queue order ----
+      constexpr int HF = OPL == 1 ? 8 : 4;
+      for (int h = sub; h < cnt; h += HF * HPI) {
+        int32_t r[HF];
+        double ww[HF];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          r[u] = L.qrow[h + u * HPI];
-          ww[u] = L.qw[h + u * HPI];
+        for (int u = 0; u < HF; ++u) {
+          const int e = h + u * HPI;
+          const int ec = e < cnt ? e : 0;
+          r[u] = L.qrow[ec];
+          ww[u] = L.qw[ec];
         }
 #pragma unroll
         for (int j = 0; j < OPL; ++j) {
           const int o = ol + j * WAVE;
           if (o < m) {
-            double a[4];
+            double a[HF];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) a[u] = M.alpha[(int64_t)r[u] * M.ms + o];
+            for (int u = 0; u < HF; ++u) a[u] = M.alpha[(int64_t)r[u] * M.ms + o];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc[j] = fma(ww[u], a[u], acc[j]);
+            for (int u = 0; u < HF; ++u)
+              if (h + u * HPI < cnt) acc[j] = fma(ww[u], a[u], acc[j]);
           }
-        }
-      }
-      for (; h < cnt; h += HPI) {
-        const int32_t r = L.qrow[h];
-        const double ww = L.qw[h];
-#pragma unroll
-        for (int j = 0; j < OPL; ++j) {
-          const int o = ol + j * WAVE;
-          if (o < m) acc[j] = fma(ww, M.alpha[(int64_t)r * M.ms + o], acc[j]);
         }
       }
       wave_sync();

@@ -35,6 +35,30 @@ __device__ __forceinline__ int32_t lookup_row(const TupDesc &T, uint32_t slot, c
   }
 }
 
+// One group of level multi-indices, one per lane (lane < 0: none): the
+// basis product at the staged point xs (eq (3.1)-(3.2)) and the row of the
+// active cell through the directory (-1 if not stored).
+__device__ __forceinline__ void group_lookup(const ModelView &M, const double *xs, int lane, const TupDesc &T,
+                                             int32_t &row, double &w) {
+  row = -1;
+  w = 0.0;
+  if (lane < 0 || T.k == 0) return;
+  double ww = T.w;
+  uint32_t slot = 0;
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    if (q < T.k) {
+      uint32_t half, c;
+      double phi, tt;
+      active_cell(xs[T.dims[q]], T.lv[q], half, phi, tt, c);
+      ww *= phi;
+      slot = (slot << (T.lv[q] - 1)) | half;
+    }
+  }
+  w = ww;
+  if (ww != 0.0) row = lookup_row(T, slot, M.tab);
+}
+
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 // Make LDS writes of one lane visible to the other lanes of the same wave.
