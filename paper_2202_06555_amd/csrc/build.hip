@@ -30,6 +30,7 @@
 #include <cstdlib>
 #include <limits>
 #include <cstring>
+#include <thread>
 #include <unordered_map>
 
 #include "kernels_common.h"
@@ -209,6 +210,23 @@ struct CompState {
   std::vector<int32_t> tuples;                                // build tuple ids
   std::vector<NodeKey> pending;                               // nodes of the next step
 };
+
+// f(begin, end) over [0, n) split into contiguous ranges, one per host
+// thread (at most 16; one range when n is small).  Every range's work must be
+// independent of the others'.
+template <typename F>
+void parallel_ranges(int64_t n, int64_t grain, F f) {
+  const int64_t hw = std::max<int64_t>(1, std::min<int64_t>(16, (int64_t)std::thread::hardware_concurrency()));
+  const int64_t T = std::max<int64_t>(1, std::min<int64_t>(hw, n / std::max<int64_t>(grain, 1)));
+  if (T <= 1) {
+    f((int64_t)0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve((size_t)T);
+  for (int64_t i = 0; i < T; ++i) th.emplace_back([&f, n, T, i]() { f(n * i / T, n * (i + 1) / T); });
+  for (auto &x : th) x.join();
+}
 
 template <typename T>
 int grow_device(T **ptr, int64_t *cap, int64_t need, int64_t used) {
@@ -427,22 +445,24 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
     clk.lap(PhaseClock::CALL);
     // ---- nodal values: g = f(xbar \ x_S), u = nested differences ----
     std::vector<double> yv((size_t)N * M2);
-    std::vector<double> buf((size_t)m << KMAX);
-    for (int64_t j = 0; j < N; ++j) {
-      const CompState &c = C[nn[j].comp];
-      const int nsub = 1 << c.k;
-      for (int v = 0; v < nsub; ++v) {
-        const int64_t r = ref[(size_t)(j << KMAX) + v];
-        const double *src = r >= 0 ? &cache_val[(size_t)r * m] : &Y[(size_t)(ncache_new + (-r - 2)) * m];
-        std::memcpy(&buf[(size_t)v * m], src, sizeof(double) * m);
+    parallel_ranges(N, 4096, [&](int64_t j0, int64_t j1) {
+      std::vector<double> buf((size_t)m << KMAX);
+      for (int64_t j = j0; j < j1; ++j) {
+        const CompState &c = C[nn[j].comp];
+        const int nsub = 1 << c.k;
+        for (int v = 0; v < nsub; ++v) {
+          const int64_t r = ref[(size_t)(j << KMAX) + v];
+          const double *src = r >= 0 ? &cache_val[(size_t)r * m] : &Y[(size_t)(ncache_new + (-r - 2)) * m];
+          std::memcpy(&buf[(size_t)v * m], src, sizeof(double) * m);
+        }
+        for (int o = 0; o < m; ++o) yv[(size_t)j * M2 + o] = buf[(size_t)(nsub - 1) * m + o];
+        for (int q = 0; q < c.k; ++q)
+          for (int v = 0; v < nsub; ++v)
+            if ((v >> q) & 1)
+              for (int o = 0; o < m; ++o) buf[(size_t)v * m + o] -= buf[(size_t)(v ^ (1 << q)) * m + o];
+        for (int o = 0; o < m; ++o) yv[(size_t)j * M2 + m + o] = buf[(size_t)(nsub - 1) * m + o];
       }
-      for (int o = 0; o < m; ++o) yv[(size_t)j * M2 + o] = buf[(size_t)(nsub - 1) * m + o];
-      for (int q = 0; q < c.k; ++q)
-        for (int v = 0; v < nsub; ++v)
-          if ((v >> q) & 1)
-            for (int o = 0; o < m; ++o) buf[(size_t)v * m + o] -= buf[(size_t)(v ^ (1 << q)) * m + o];
-      for (int o = 0; o < m; ++o) yv[(size_t)j * M2 + m + o] = buf[(size_t)(nsub - 1) * m + o];
-    }
+    });
     clk.lap(PhaseClock::NODAL);
     // ---- device: hierarchise against the existing directory ----
     std::vector<NodeDev> nd((size_t)N);
@@ -583,46 +603,58 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
     rows_used += N;
     clk.lap(PhaseClock::DIRECTORY);
     // ---- children of accepted nodes (Sec. 3.1 exclusion rule) ----
-    for (int64_t j = 0; j < N; ++j) {
-      if (!acc[j]) continue;
-      CompState &c = C[nn[j].comp];
-      const NodeKey &key = nn[j].key;
-      int32_t ls = 0;
-      for (int q = 0; q < c.k; ++q) ls += key.l[q];
-      if (P->level_rule == 1 && ls + 1 > P->max_level + c.k - 1) continue;
-      for (int q = 0; q < c.k; ++q) {
-        if (P->level_rule == 0 && key.l[q] + 1 > P->max_level) continue;
-        for (int side = -1; side <= 1; side += 2) {
-          NodeKey ch = key;
-          ch.l[q] = (uint8_t)(ch.l[q] + 1);
-          ch.i[q] = 2 * ch.i[q] + side;
-          int npar = 0, nacc = 0;
-          for (int p = 0; p < c.k; ++p) {
-            if (ch.l[p] <= 1) continue;
-            NodeKey par = ch;
-            par.l[p] = (uint8_t)(par.l[p] - 1);
-            const uint32_t a = (ch.i[p] - 1) / 2, b = (ch.i[p] + 1) / 2;
-            par.i[p] = (a & 1u) ? a : b;
-            ++npar;
-            auto it = c.index.find(par);
-            if (it != c.index.end() && c.acc[it->second]) ++nacc;
+    // The nodes are grouped by component (nn is sorted by component) and a
+    // component's nodes stay in one thread, so each pending list is built in
+    // the same order as by one thread.
+    std::vector<int64_t> cstart;
+    for (int64_t j = 0; j < N; ++j)
+      if (j == 0 || nn[j].comp != nn[j - 1].comp) cstart.push_back(j);
+    cstart.push_back(N);
+    parallel_ranges((int64_t)cstart.size() - 1, 8, [&](int64_t g0, int64_t g1) {
+      for (int64_t j = cstart[(size_t)g0]; j < cstart[(size_t)g1]; ++j) {
+        if (!acc[j]) continue;
+        CompState &c = C[nn[j].comp];
+        const NodeKey &key = nn[j].key;
+        int32_t ls = 0;
+        for (int q = 0; q < c.k; ++q) ls += key.l[q];
+        if (P->level_rule == 1 && ls + 1 > P->max_level + c.k - 1) continue;
+        for (int q = 0; q < c.k; ++q) {
+          if (P->level_rule == 0 && key.l[q] + 1 > P->max_level) continue;
+          for (int side = -1; side <= 1; side += 2) {
+            NodeKey ch = key;
+            ch.l[q] = (uint8_t)(ch.l[q] + 1);
+            ch.i[q] = 2 * ch.i[q] + side;
+            int npar = 0, nacc = 0;
+            for (int p = 0; p < c.k; ++p) {
+              if (ch.l[p] <= 1) continue;
+              NodeKey par = ch;
+              par.l[p] = (uint8_t)(par.l[p] - 1);
+              const uint32_t a = (ch.i[p] - 1) / 2, b = (ch.i[p] + 1) / 2;
+              par.i[p] = (a & 1u) ? a : b;
+              ++npar;
+              auto it = c.index.find(par);
+              if (it != c.index.end() && c.acc[it->second]) ++nacc;
+            }
+            const bool admit = P->refine_rule == 0 ? (nacc == npar) : (nacc > 0);
+            if (admit) c.pending.push_back(ch);
           }
-          const bool admit = P->refine_rule == 0 ? (nacc == npar) : (nacc > 0);
-          if (admit) c.pending.push_back(ch);
         }
       }
-    }
-    for (auto &c : C) {
-      if (c.pending.size() < 2) continue;
-      std::sort(c.pending.begin(), c.pending.end(), [&](const NodeKey &a, const NodeKey &b) {
-        for (int q = 0; q < c.k; ++q)
-          if (a.l[q] != b.l[q]) return a.l[q] < b.l[q];
-        for (int q = 0; q < c.k; ++q)
-          if (a.i[q] != b.i[q]) return a.i[q] < b.i[q];
-        return false;
-      });
-      c.pending.erase(std::unique(c.pending.begin(), c.pending.end()), c.pending.end());
-    }
+    });
+    parallel_ranges((int64_t)C.size(), 8, [&](int64_t s0, int64_t s1) {
+      for (int64_t s = s0; s < s1; ++s) {
+        CompState &c = C[(size_t)s];
+        if (c.pending.size() < 2) continue;
+        std::sort(c.pending.begin(), c.pending.end(), [&](const NodeKey &a, const NodeKey &b) {
+          for (int q = 0; q < c.k; ++q)
+            if (a.l[q] != b.l[q]) return a.l[q] < b.l[q];
+          for (int q = 0; q < c.k; ++q)
+            if (a.i[q] != b.i[q]) return a.i[q] < b.i[q];
+          return false;
+        });
+        c.pending.erase(std::unique(c.pending.begin(), c.pending.end()), c.pending.end());
+      }
+    });
     clk.lap(PhaseClock::CHILDREN);
   }
   return HDMR_OK;
