@@ -603,7 +603,8 @@ def bench_grad(args):
                                "points; gradient n x d x m FP64", "grid_rows": hd.hdmr_get_info(model)["n_rows"]},
         "roofline": {"bound": "mfma", "achieved": flops_launch / per_launch_s / 1e12, "peak": FP64_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": flops_launch / per_launch_s / FP64_PEAK, "traffic": None,
-                     "kernel": "k_tile_fp64<48, true> (cell-sorted contraction with derivative chains)",
+                     "kernel": "k_tile_fp64<56, true, true> (cell-sorted contraction with derivative chains; "
+                               "m <= 16, so the waves split each sub-tile's points)",
                      "launches_per_step": c_launches / args.steps, "avg_launch_ms": per_launch_s * 1e3,
                      "algorithmic_flops_per_launch": flops_launch,
                      "note": "2 m (value products + derivative products); k derivative products per nonzero "

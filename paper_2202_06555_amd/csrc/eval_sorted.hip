@@ -251,31 +251,37 @@ __device__ int cell_rows(const ModelView &M, const Pass &P, const PassTup *__res
   return nrows;
 }
 
-// Rows and work items of every nonempty cell of a pass.  A workgroup takes
+// Rows (and work items) of the cells of a pass.  A workgroup takes
 // SETUP_CELLS consecutive cells (each wave SETUP_CELLS / 4 of them): it counts
-// every cell's rows, claims one range of the row list and one of the
-// work-item list for all its cells with one atomic add each (counters[0],
-// counters[1]; the latter ends as the number of items), then writes the rows
-// and the items (first sorted point, count <= chunk, rows of the cell, first
-// row entry).  The order of the workgroups' ranges in the lists depends on
-// scheduling; no point's result does (a point's sums run over its own cell's
-// rows in their directory order).
+// every cell's rows, claims one range of the row list (counters[0]) for all
+// its cells with one atomic add, and writes the rows.
+//   bstart == NULL: every cell, occupied or not (the rows depend on the model
+//     and the pass only, so this runs before the points are sorted); the
+//     cell's (first row entry, rows) go to crow[cell];
+//   otherwise: the occupied cells only, and also their work items (first
+//     sorted point, count <= chunk, rows of the cell, first row entry),
+//     claimed the same way (counters[1] ends as the number of items).
+// The order of the workgroups' ranges in the lists depends on scheduling; no
+// point's result does (a point's sums run over its own cell's rows in their
+// directory order).
 constexpr int SETUP_CELLS = 16;
 __global__ __launch_bounds__(256) void k_cell_setup(ModelView M, Pass P, const PassTup *__restrict__ ptups,
                                                     const uint32_t *__restrict__ bstart,
                                                     const uint32_t *__restrict__ bend, int nbins, uint32_t chunk,
                                                     CellRow *__restrict__ list, uint4 *__restrict__ idx,
-                                                    uint4 *__restrict__ tiles, uint32_t *__restrict__ counters) {
+                                                    uint2 *__restrict__ crow, uint4 *__restrict__ tiles,
+                                                    uint32_t *__restrict__ counters) {
   __shared__ uint32_t s_nr[SETUP_CELLS], s_nt[SETUP_CELLS], s_ro[SETUP_CELLS], s_to[SETUP_CELLS], s_base[2];
   const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
   constexpr int PER_WAVE = SETUP_CELLS / WAVES_PER_BLOCK;
+  const bool all = bstart == nullptr;
   const int64_t c0 = (int64_t)blockIdx.x * SETUP_CELLS;
   for (int c = wid * PER_WAVE; c < (wid + 1) * PER_WAVE; ++c) {
     const int64_t bin = c0 + c;
     uint32_t nr = 0, nt = 0;
-    if (bin < nbins && bend[bin] > bstart[bin]) {
+    if (bin < nbins && (all || bend[bin] > bstart[bin])) {
       nr = (uint32_t)cell_rows(M, P, ptups, (uint32_t)bin, 0u, nullptr, nullptr, lane);
-      nt = (bend[bin] - bstart[bin] + chunk - 1) / chunk;
+      if (!all) nt = (bend[bin] - bstart[bin] + chunk - 1) / chunk;
     }
     if (lane == 0) {
       s_nr[c] = nr;
@@ -297,6 +303,11 @@ __global__ __launch_bounds__(256) void k_cell_setup(ModelView M, Pass P, const P
   __syncthreads();
   for (int c = wid * PER_WAVE; c < (wid + 1) * PER_WAVE; ++c)
     if (s_nr[c]) cell_rows(M, P, ptups, (uint32_t)(c0 + c), s_base[0] + s_ro[c], list, idx, lane);
+  if (all) {
+    if (threadIdx.x < SETUP_CELLS && c0 + threadIdx.x < nbins)
+      crow[c0 + threadIdx.x] = make_uint2(s_base[0] + s_ro[threadIdx.x], s_nr[threadIdx.x]);
+    return;
+  }
   for (int c = 0; c < SETUP_CELLS; ++c) {
     const int64_t bin = c0 + c;
     for (uint32_t q = threadIdx.x; q < s_nt[c]; q += blockDim.x) {
@@ -305,6 +316,44 @@ __global__ __launch_bounds__(256) void k_cell_setup(ModelView M, Pass P, const P
                                                   s_base[0] + s_ro[c]);
     }
   }
+}
+
+// Work items of the occupied cells once their rows are known (crow, from
+// k_cell_setup over every cell): a workgroup takes 256 consecutive cells, one
+// per thread, and claims its range of the item list with one atomic add.
+__global__ __launch_bounds__(256) void k_cell_tiles(const uint32_t *__restrict__ bstart,
+                                                    const uint32_t *__restrict__ bend, const uint2 *__restrict__ crow,
+                                                    int nbins, uint32_t chunk, uint4 *__restrict__ tiles,
+                                                    uint32_t *__restrict__ counters) {
+  __shared__ uint32_t s_scan[256];
+  __shared__ uint32_t s_base;
+  const int64_t bin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t s0 = 0, cnt = 0, nt = 0;
+  if (bin < nbins) {
+    s0 = bstart[bin];
+    cnt = bend[bin] - s0;
+    nt = (cnt + chunk - 1) / chunk;
+  }
+  s_scan[threadIdx.x] = nt;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {  // inclusive scan (Hillis-Steele)
+    const uint32_t v = threadIdx.x >= (unsigned)off ? s_scan[threadIdx.x - off] : 0u;
+    __syncthreads();
+    s_scan[threadIdx.x] += v;
+    __syncthreads();
+  }
+  if (threadIdx.x == 255) s_base = s_scan[255] ? atomicAdd(&counters[1], s_scan[255]) : 0u;
+  __syncthreads();
+  if (nt) {
+    const uint2 cr = crow[bin];
+    const uint32_t first = s_base + s_scan[threadIdx.x] - nt;
+    for (uint32_t q = 0; q < nt; ++q)
+      tiles[first + q] = make_uint4(s0 + q * chunk, min(cnt - q * chunk, chunk), cr.y, cr.x);
+  }
+}
+
+__global__ void k_zero_u32(uint32_t *__restrict__ a, int n) {
+  if ((int)threadIdx.x < n) a[threadIdx.x] = 0u;
 }
 
 // Basis weight of a point with key coordinates x0..x3 for one stored row:
@@ -1020,6 +1069,7 @@ struct PassBufs {
   int32_t *idx, *spid;
   double *xk;
   uint32_t *bstart, *bend, *counters;  // counters: rows appended, work items appended
+  uint2 *crow;                          // per cell: first row entry, rows (rows computed before the sort)
   CellRow *clist;
   uint4 *cidx, *tiles;
   void *tmp;
@@ -1049,6 +1099,7 @@ void carve_workspace(Carve &C, Workspace &W, int64_t n, int d, int AS, bool mixe
     B.bstart = C.take<uint32_t>(65536);
     B.bend = C.take<uint32_t>(65536);
     B.counters = C.take<uint32_t>(2);
+    B.crow = C.take<uint2>(65536);
     B.clist = C.take<CellRow>((size_t)list_max);
     B.cidx = C.take<uint4>((size_t)list_max);
     B.tiles = C.take<uint4>(max_tiles);
@@ -1224,6 +1275,17 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
     // keys, sort and row discovery of this pass on the second stream, once
     // the contraction NBUF passes back is done with this buffer set
     if (pi >= NBUF && (e = hipStreamWaitEvent(side, ev_done[bsel], 0)) != hipSuccess) break;
+    // with most cells occupied, the rows of every cell are found before the
+    // sort (they depend on the model and the pass only), and only the work
+    // items wait for the cell bounds
+    const bool rows_first = (int64_t)nbins * 4 <= n;
+    if (rows_first) {
+      StageTimer tm(STAGE_ROWS, side);
+      hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, side, B.counters, 2);
+      hipLaunchKernelGGL(k_cell_setup, dim3(gc), dim3(256), 0, side, M, P, model->pass_tups,
+                         (const uint32_t *)nullptr, (const uint32_t *)nullptr, nbins, chunk, B.clist, B.cidx, B.crow,
+                         B.tiles, B.counters);
+    }
     {
       StageTimer tm(STAGE_SORT, side);
       hipLaunchKernelGGL(k_keys, dim3(gs), dim3(256), 0, side, W.xt, n, P, B.key, B.idx, B.xk, B.bstart, B.bend,
@@ -1234,10 +1296,14 @@ int eval_sorted(const hdmr_model *model, const double *X, int64_t n, double *F, 
       hipLaunchKernelGGL(k_bounds, dim3(gs), dim3(256), 0, side, B.key_s, n, B.bstart, B.bend);
     }
     {
-      // rows and work items of every nonempty cell
+      // work items (and, if not found before the sort, rows) of every occupied cell
       StageTimer tm(STAGE_ROWS, side);
-      hipLaunchKernelGGL(k_cell_setup, dim3(gc), dim3(256), 0, side, M, P, model->pass_tups, B.bstart, B.bend, nbins,
-                         chunk, B.clist, B.cidx, B.tiles, B.counters);
+      if (rows_first)
+        hipLaunchKernelGGL(k_cell_tiles, dim3((unsigned)((nbins + 255) / 256)), dim3(256), 0, side, B.bstart, B.bend,
+                           B.crow, nbins, chunk, B.tiles, B.counters);
+      else
+        hipLaunchKernelGGL(k_cell_setup, dim3(gc), dim3(256), 0, side, M, P, model->pass_tups, B.bstart, B.bend,
+                           nbins, chunk, B.clist, B.cidx, B.crow, B.tiles, B.counters);
     }
     if ((e = hipEventRecord(ev_sorted[bsel], side)) != hipSuccess) break;
     if ((e = hipStreamWaitEvent(stream, ev_sorted[bsel], 0)) != hipSuccess) break;
