@@ -31,6 +31,16 @@
  *     a NaN coordinate makes every output (and gradient entry) of that point NaN.
  *   - Limits: |S| <= 4 per component, d <= 32767, 1 <= level <= 30, and
  *     sum_q (l_q - 1) <= 31 for each stored level multi-index.
+ *   - Environment variables (diagnostics and tests; only HDMR_MIXED_SPLIT
+ *     changes a result, within the mixed path's error):
+ *     HDMR_EVAL_PATH=gather|sorted forces hdmr_eval's kernel;
+ *     HDMR_SORTED_VARIANT=<bits> selects another tile shape of the cell-sorted
+ *     kernel; HDMR_BATCH_PATH=gather|sorted replaces hdmr_eval_batched's
+ *     measured choice; HDMR_MIXED_SPLIT=2 keeps two BF16 terms instead of
+ *     three; HDMR_BUILD_PROFILE=1 prints the build's phase times to stderr;
+ *     HDMR_FAIL_ALLOC=k makes the library's device allocation number k
+ *     (counted from when the variable takes that value) fail, so that the
+ *     HDMR_ENOMEM paths can be tested from the host.
  */
 #ifndef HDMR_H
 #define HDMR_H
@@ -251,8 +261,8 @@ void hdmr_free(hdmr_model *model);
 /* Per-kernel device timing (diagnostic; not part of the method).  While
  * enabled, the evaluation brackets each stage of every pass with device
  * events recorded on the launch stream.  The stages are:
- *   "sort"     -- keys, radix sort, cell bounds, tiles, sorted coordinates;
- *   "rows"     -- per-cell row discovery: count, scan, write;
+ *   "sort"     -- keys and key coordinates, radix sort, cell bounds;
+ *   "rows"     -- per-cell row discovery and the work items of the cells;
  *   "contract" -- the matrix-core contraction of the tiles.
  * hdmr_timing_enable(on): on != 0 enables timing and discards earlier
  * records; on == 0 disables it and discards them.

@@ -186,7 +186,8 @@ void probe_rmw() {
   struct Layout {
     const char *name;
     int stride, width, colblock;
-  } layouts[] = {{"rowmajor_m51", 51, 51, 0}, {"rowmajor_pad64", 64, 64, 0}, {"colblock16_m64", 16, 64, 1}};
+  } layouts[] = {{"rowmajor_m51", 51, 51, 0},   {"rowmajor_pad64", 64, 64, 0}, {"colblock16_m64", 16, 64, 1},
+                 {"rowmajor_pad56", 56, 56, 0}, {"rowmajor_pad48", 48, 48, 0}};
   const int64_t max_rows = sizes[0];
   double *F = nullptr;
   int32_t *perm_d = nullptr;
