@@ -220,3 +220,23 @@ def test_four_dim_components(hd):
     ok = ~np.isnan(X).any(axis=1)
     import _fullsize as fs
     assert fs.per_output_rel(Ym[ok], ref[ok]) <= 1e-6
+
+
+@pytest.mark.parametrize("variant", [1, 2, 4, 8, 15])
+def test_sorted_tile_shapes(hd, eval_path, variant, monkeypatch):
+    """Every tile shape of the cell-sorted path (HDMR_SORTED_VARIANT bits: the
+    smaller row batch, work items of half the points, persistent grids of three
+    or two workgroups per CU) on a ragged batch with special points: plain at
+    1e-12 and mixed at the per-output bar against the oracle."""
+    if eval_path != "sorted":
+        pytest.skip("tile shapes belong to the cell-sorted path")
+    monkeypatch.setenv("HDMR_SORTED_VARIANT", str(variant))
+    model = ws.synthetic_regular_model(d=6, m=37, order=2, ell=6, seed=40 + variant)
+    rng = np.random.default_rng(variant)
+    X = _special_points(6, rng, 20011)
+    gm, Y = _eval(hd, model, X)
+    ref = oracle.evaluate(model, X)
+    assert np.abs(Y - ref).max() <= TOL
+    Ym = hd.hdmr_eval(gm, _dev(X), precision=hd.MIXED).cpu().numpy()
+    per_output = (np.abs(Ym - ref).max(axis=0) / np.abs(ref).max(axis=0)).max()
+    assert per_output <= 1e-6, per_output
