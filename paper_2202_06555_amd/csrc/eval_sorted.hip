@@ -150,6 +150,7 @@ __global__ void k_bounds(const uint16_t *__restrict__ ks, int64_t n, uint32_t *_
 }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -535,7 +536,9 @@ __device__ __forceinline__ int p_off(int pt, int c) { return pt * 64 + (c ^ ((pt
 
 // Adds the parked sums of a sub-tile (s_o at p_off(pt, c), c < ncols) to the
 // FP64 accumulator rows acc + pid[pt] * AS + o0: 16-byte pieces, all loads of
-// a thread in flight before its stores.  NARROW: ncols == 16.
+// a thread in flight before its stores.  NARROW: ncols == 16.  The rows are
+// touched once per pass, so their loads and stores are non-temporal: they
+// stream past the caches, which keep the cell rows and surplus operands.
 template <bool NARROW>
 __device__ __forceinline__ void add_parked_f64(double *__restrict__ acc, int AS, int o0, int ncols,
                                                const int32_t *pid, int cnt, const double *s_o, int t) {
@@ -545,53 +548,48 @@ __device__ __forceinline__ void add_parked_f64(double *__restrict__ acc, int AS,
   const int c2 = t % CP, pr = t / CP;
   const bool col_on = 2 * c2 < ncols;
   double *base = acc + o0 + 2 * c2;
-  double2 v[NI];
+  v2d v[NI];
   int32_t p[NI];
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
     const int pt = pr + PR * i;
     p[i] = (col_on && pt < cnt) ? pid[pt] : -1;
-    v[i] = p[i] >= 0 ? *reinterpret_cast<const double2 *>(base + (int64_t)p[i] * AS) : make_double2(0.0, 0.0);
+    v[i] = p[i] >= 0 ? __builtin_nontemporal_load(reinterpret_cast<const v2d *>(base + (int64_t)p[i] * AS))
+                     : v2d{0.0, 0.0};
   }
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
     const int pt = pr + PR * i;
     if (p[i] >= 0) {
-      double2 r = v[i];
-      const double2 s = *reinterpret_cast<const double2 *>(s_o + p_off(pt, 2 * c2));
-      r.x += s.x;
-      r.y += s.y;
-      *reinterpret_cast<double2 *>(base + (int64_t)p[i] * AS) = r;
+      const v2d r = v[i] + *reinterpret_cast<const v2d *>(s_o + p_off(pt, 2 * c2));
+      __builtin_nontemporal_store(r, reinterpret_cast<v2d *>(base + (int64_t)p[i] * AS));
     }
   }
 }
 
-// The same for FP32 accumulators (float4 pieces, ncols <= 64).
+// The same for FP32 accumulators (float4 pieces, ncols <= 64), non-temporal too.
 __device__ __forceinline__ void add_parked_f32(float *__restrict__ acc, int AS, int o0, int ncols, const int32_t *pid,
                                                int cnt, const float *s_o, int t) {
   constexpr int CQ = 16, PR = 256 / CQ, NI = TPTS / PR;
   const int c4 = t % CQ, pr = t / CQ;
   const bool col_on = 4 * c4 < ncols;
   float *base = acc + o0 + 4 * c4;
-  float4 v[NI];
+  v4f v[NI];
   int32_t p[NI];
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
     const int pt = pr + PR * i;
     p[i] = (col_on && pt < cnt) ? pid[pt] : -1;
-    v[i] = p[i] >= 0 ? *reinterpret_cast<const float4 *>(base + (int64_t)p[i] * AS) : make_float4(0.f, 0.f, 0.f, 0.f);
+    v[i] = p[i] >= 0 ? __builtin_nontemporal_load(reinterpret_cast<const v4f *>(base + (int64_t)p[i] * AS))
+                     : v4f{0.f, 0.f, 0.f, 0.f};
   }
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
     const int pt = pr + PR * i;
     if (p[i] >= 0) {
       const float *o = s_o + pt * OS32 + 4 * c4;
-      float4 r = v[i];
-      r.x += o[0];
-      r.y += o[1];
-      r.z += o[2];
-      r.w += o[3];
-      *reinterpret_cast<float4 *>(base + (int64_t)p[i] * AS) = r;
+      const v4f r = v[i] + v4f{o[0], o[1], o[2], o[3]};
+      __builtin_nontemporal_store(r, reinterpret_cast<v4f *>(base + (int64_t)p[i] * AS));
     }
   }
 }
