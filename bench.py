@@ -85,6 +85,7 @@ def main():
     ap.add_argument("--train-points", type=int, default=2_000_000, help="surrogate: interpolant training pairs")
     ap.add_argument("--epochs", type=int, default=3, help="surrogate: passes over the training pairs")
     ap.add_argument("--serve-points", type=int, default=2_000_000, help="surrogate: points served")
+    ap.add_argument("--ti-steps", type=int, default=4, help="irbc: time-iteration steps after the residual timing")
     ap.add_argument("--train-seconds", type=float, default=0.0,
                     help="surrogate: train in one-epoch segments for this long (0: --epochs in one run)")
     args = ap.parse_args()
@@ -541,6 +542,7 @@ def bench_irbc(args):
                    "next_state_evals_per_s": n * Q * (N + 1) / t,
                    "hdmr_eval_ms_same_count_uniform_points": t_eval * 1e3},
     }
+    out["config"]["time_iteration"] = time_iteration(hd, irbc, ws, args.ti_steps)
     if not args.no_cpu_baseline:
         import oracle
         from oracle import irbc as oirbc
@@ -554,6 +556,47 @@ def bench_irbc(args):
         out["cpu_baseline"] = {"value": k / tc, "unit": "states/s", "cores": oracle.num_threads(), "kind": "oracle",
                                "sample": "first %d states" % k}
     print(json.dumps(out), flush=True)
+
+
+def time_iteration(hd, irbc, ws, steps, N=10):
+    """Time iteration (Alg. 1) on the smooth IRBC model with N countries
+    (d = 2N, m = N + 1) from the synthetic policy: each step is a build whose
+    function is the device Newton solve of the first-order conditions at the
+    build's nodes, with the previous policy inside the expectation (L = 5,
+    eps_gamma = 1e-5, Newton tolerance 1e-11).  After every step: the Euler
+    errors (Sec. 5) of the new policy on 10^4 uniform states, and the largest
+    change of the policy there (the stopping test of Alg. 1)."""
+    import numpy as np
+    import torch
+    p = ws.irbc_params(N)
+    g = ws.IrbcGuess(N)
+    comps = g.components()
+    X, _ = ws.irbc_states(10_000, N, seed=41)
+    Xd = torch.from_numpy(X).to("cuda:0")
+    pol = hd.asg_build_components(g.d, g.m, g.anchor, g, comps=comps, max_level=5, eps_gamma=1e-5)
+
+    def errs(model):
+        e = irbc.irbc_euler_errors(model, p, Xd).cpu().numpy()
+        return {"euler_log10_mean": float(np.log10(e[:, :N]).mean()),
+                "euler_log10_max": float(np.log10(e[:, :N].max())),
+                "resource_log10_max": float(np.log10(e[:, N].max()))}
+
+    rec = [{"step": 0, **errs(pol)}]
+    prev_vals = hd.hdmr_eval(pol, Xd).cpu().numpy()
+    for s in range(1, steps + 1):
+        t0 = time.perf_counter()
+        new, iters, worst = irbc.irbc_time_step(pol, p, comps, max_level=5, eps_gamma=1e-5, max_iter=20, tol=1e-11)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        vals = hd.hdmr_eval(new, Xd).cpu().numpy()
+        r = {"step": s, "seconds": dt, "newton_iterations_max": int(iters), "newton_residual_max": float(worst),
+             "grid_rows": hd.hdmr_get_info(new)["n_rows"], "policy_change_max": float(np.abs(vals - prev_vals).max()),
+             **errs(new)}
+        rec.append(r)
+        log("time-iteration step %d: %.2f s, %d rows, policy change %.2e, Euler errors log10 mean %.2f max %.2f" %
+            (s, dt, r["grid_rows"], r["policy_change_max"], r["euler_log10_mean"], r["euler_log10_max"]))
+        pol, prev_vals = new, vals
+    return {"N": N, "d": 2 * N, "m": N + 1, "states_for_errors": X.shape[0], "steps": rec}
 
 
 def bench_grad(args):
