@@ -85,7 +85,7 @@ def main():
     ap.add_argument("--train-points", type=int, default=2_000_000, help="surrogate: interpolant training pairs")
     ap.add_argument("--epochs", type=int, default=3, help="surrogate: passes over the training pairs")
     ap.add_argument("--serve-points", type=int, default=2_000_000, help="surrogate: points served")
-    ap.add_argument("--ti-steps", type=int, default=4, help="irbc: time-iteration steps after the residual timing")
+    ap.add_argument("--ti-steps", type=int, default=6, help="irbc: time-iteration steps after the residual timing")
     ap.add_argument("--train-seconds", type=float, default=0.0,
                     help="surrogate: train in one-epoch segments for this long (0: --epochs in one run)")
     args = ap.parse_args()
