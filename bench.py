@@ -3,8 +3,9 @@ expansion with adaptive sparse-grid components.  Default workload: d=100,
 100 one-dimensional + 500 two-dimensional components, adaptive grids to level
 8 with eps_gamma = 1e-4, m = 51 outputs, 4e6 next-state points.
 
-One step = one hdmr_eval over all points, inputs resident in HBM.  Prints one
-JSON line.  The model is built on the device with asg_build_components from
+One step = one hdmr_eval over all points, inputs resident in HBM; the
+default runs the plain FP64 leg (the headline value) and the mixed leg (the
+"mixed" object).  Prints one JSON line.  The model is built on the device with asg_build_components from
 the seeded synthetic test function (untimed).  The device time of every
 evaluation stage is taken live with device events on the launch stream
 (hdmr_timing_*); the roofline object prices the dominant kernel, the
@@ -16,8 +17,9 @@ per evaluation), the bytes this design moves (16 per point and output per
 pass for the output read-modify-write), and the HBM traffic measured with
 rocprofv3 FETCH_SIZE + WRITE_SIZE (profiles/, copy-calibrated).
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision plain|mixed]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision both|plain|mixed]
                   [--no-cpu-baseline] [--points N] [--calibrate-copy]
+                  [--workload eval|grad|naive|irbc|batched|surrogate]
 """
 import argparse
 import hashlib
