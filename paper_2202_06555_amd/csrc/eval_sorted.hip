@@ -598,6 +598,8 @@ __device__ __forceinline__ void add_parked_f32(float *__restrict__ acc, int AS, 
 // (the gradient: lane value (group mt, register i) belongs to point
 // mt * 16 + r0 + i * rs of the sub-tile and output col; point p's row starts
 // at F + p * m).  Two halves of 8 loads keep the live registers bounded.
+// Like the accumulator rows, the gradient rows are touched once per pass and
+// key dimension, so they are loaded and stored non-temporally.
 template <typename V, typename S>
 __device__ __forceinline__ void add_rows(double *__restrict__ F, const int32_t *pid, S m, int col, int cnt, int r0,
                                          int rs, const V (&acc)[4]) {
@@ -609,14 +611,14 @@ __device__ __forceinline__ void add_rows(double *__restrict__ F, const int32_t *
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int pt = (2 * h + a) * 16 + r0 + i * rs;
-        f[a][i] = pt < cnt ? F[(int64_t)pid[pt] * m + col] : 0.0;
+        f[a][i] = pt < cnt ? __builtin_nontemporal_load(F + (int64_t)pid[pt] * m + col) : 0.0;
       }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int pt = (2 * h + a) * 16 + r0 + i * rs;
-        if (pt < cnt) F[(int64_t)pid[pt] * m + col] = f[a][i] + (double)acc[2 * h + a][i];
+        if (pt < cnt) __builtin_nontemporal_store(f[a][i] + (double)acc[2 * h + a][i], F + (int64_t)pid[pt] * m + col);
       }
   }
 }
@@ -630,12 +632,12 @@ __device__ __forceinline__ void add_group(double *__restrict__ F, const int32_t 
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int pt = p0 + i * rs;
-    f[i] = pt < cnt ? F[(int64_t)pid[pt] * m + col] : 0.0;
+    f[i] = pt < cnt ? __builtin_nontemporal_load(F + (int64_t)pid[pt] * m + col) : 0.0;
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int pt = p0 + i * rs;
-    if (pt < cnt) F[(int64_t)pid[pt] * m + col] = f[i] + acc[i];
+    if (pt < cnt) __builtin_nontemporal_store(f[i] + acc[i], F + (int64_t)pid[pt] * m + col);
   }
 }
 
