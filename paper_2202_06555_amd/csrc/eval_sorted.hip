@@ -1016,20 +1016,22 @@ __global__ __launch_bounds__(256, 3) void k_tile_mixed(ModelView M, Pass P, cons
 __global__ void k_init_acc(double *__restrict__ acc, const double *__restrict__ c0, int64_t n, int m, int AS) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * AS; e += (int64_t)gridDim.x * blockDim.x) {
     const int o = (int)(e % AS);
-    acc[e] = o < m ? c0[o] : 0.0;
+    __builtin_nontemporal_store(o < m ? c0[o] : 0.0, acc + e);
   }
 }
 
 __global__ void k_zero_f32(float *__restrict__ a, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    a[i] = 0.f;
+    __builtin_nontemporal_store(0.f, a + i);
 }
 
-// FP32 partial sums folded into the FP64 accumulators (and cleared).
+// FP32 partial sums folded into the FP64 accumulators (and cleared); a
+// streaming pass, so non-temporal like the contraction's row updates.
 __global__ void k_fold(double *__restrict__ acc, float *__restrict__ acc32, int64_t total) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    acc[e] += (double)acc32[e];
-    acc32[e] = 0.f;
+    const double v = __builtin_nontemporal_load(acc + e) + (double)__builtin_nontemporal_load(acc32 + e);
+    __builtin_nontemporal_store(v, acc + e);
+    __builtin_nontemporal_store(0.f, acc32 + e);
   }
 }
 
