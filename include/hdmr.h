@@ -38,6 +38,8 @@
  *     kernel; HDMR_BATCH_PATH=gather|sorted replaces hdmr_eval_batched's
  *     measured choice; HDMR_MIXED_SPLIT=2 keeps two BF16 terms instead of
  *     three; HDMR_BUILD_PROFILE=1 prints the build's phase times to stderr;
+ *     HDMR_REFINE=host admits a build's children on the host instead of on
+ *     the device (the same grids and surpluses, bit for bit);
  *     HDMR_FAIL_ALLOC=k makes the library's device allocation number k
  *     (counted from when the variable takes that value) fail, so that the
  *     HDMR_ENOMEM paths can be tested from the host.

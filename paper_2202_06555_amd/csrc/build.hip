@@ -11,9 +11,10 @@
 //   device : k_hierarchize_fp64 -- alpha = y - (interpolant of the rows of
 //            smaller level sum at the node), for g and u together (2m
 //            columns), and the eq (3.8) test max_o |alpha^g_o| > eps_gamma;
-//   host   : the new level multi-indices join the lookup directory and the
-//            children (l + e_q, 2 i_q -+ 1) of accepted nodes are admitted by
-//            the parent rule (Sec. 3.1 exclusion).
+//   host   : the new level multi-indices join the lookup directory;
+//   device : k_refine -- the children (l + e_q, 2 i_q -+ 1) of accepted nodes
+//            are admitted by the parent rule (Sec. 3.1 exclusion), each once,
+//            and packed for the next step.
 // With the Alg. 2 criteria (eps_eta or eps_rho > 0) the expansion orders are
 // built in turn: the candidates of order k (index sets of size k that contain
 // no rejected set of Z) are grown as above, k_quadrature_rows forms the
@@ -155,6 +156,132 @@ __global__ __launch_bounds__(256) void k_quadrature_rows(const double *__restric
     __syncthreads();
     if (w == 0 && o < m) q[(int64_t)c * m + o] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
     __syncthreads();
+  }
+}
+
+// A child admitted for the next step, as k_refine hands it back.
+struct ChildDev {
+  int32_t comp;
+  uint8_t lv[KMAX];
+  uint32_t ix[KMAX];
+};
+
+// Order of a node among the nodes of one step: (component, the levels as
+// 8-bit digits, the cell slot -- the bits (i_q - 1) / 2 of every dimension in
+// turn, l_q - 1 bits each).  The host sorts each step's nodes by this key;
+// with at most 31 slot bits no two nodes share it.
+__device__ __forceinline__ void node_order(const uint8_t *lv, const uint32_t *ix, uint32_t &lk, uint32_t &sl) {
+  lk = 0;
+  sl = 0;
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q)
+    if (lv[q]) {
+      lk = (lk << 8) | lv[q];
+      sl = (sl << (lv[q] - 1)) | ((ix[q] - 1) >> 1);
+    }
+}
+
+// Position of the node (comp, lk, sl) among the step's n nodes, or -1.
+__device__ int64_t find_node(const NodeDev *__restrict__ nodes, int64_t n, int32_t comp, uint32_t lk, uint32_t sl) {
+  int64_t lo = 0, hi = n;  // first node whose key is not below the target
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    const NodeDev v = nodes[mid];
+    uint32_t vl, vs;
+    node_order(v.lv, v.ix, vl, vs);
+    const bool below = v.comp != comp ? v.comp < comp : (vl != lk ? vl < lk : vs < sl);
+    if (below) lo = mid + 1;
+    else hi = mid;
+  }
+  if (lo == n) return -1;
+  const NodeDev v = nodes[lo];
+  uint32_t vl, vs;
+  node_order(v.lv, v.ix, vl, vs);
+  return (v.comp == comp && vl == lk && vs == sl) ? lo : -1;
+}
+
+// The Sec. 3.1 refinement of one step on the device.  One thread per
+// candidate t = (node j, dimension q, side): the child (l + e_q, 2 i_q -+ 1)
+// of node j, considered when j was accepted (eq (3.8)), q < |S| and the level
+// limit allows it.  Its parents -- the child with one level lowered, in each
+// dimension whose level exceeds 1 -- have the step's level sum, so they are
+// all among the step's nodes, found by binary search.  Rule 0 admits the child
+// when every parent is accepted, rule 1 when one is (node j itself is one).
+// A child with several parents is emitted once: under rule 0 by its parent in
+// the lowest dimension with a parent, under rule 1 by its accepted parent in
+// the lowest such dimension.  Emitted children are packed into
+// out[0 .. *count) with one ballot and one atomic per wave; their order varies
+// from run to run, and the next step sorts them.
+__global__ __launch_bounds__(256) void k_refine(const NodeDev *__restrict__ nodes,
+                                                const uint8_t *__restrict__ accepted, int64_t n, int max_level,
+                                                int level_rule, int refine_rule, ChildDev *__restrict__ out,
+                                                uint32_t *__restrict__ count) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t ncand = n * (2 * KMAX);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // the lanes of a wave share t0, so they leave the loop together
+  for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(WAVE - 1)); t0 < ncand; t0 += stride) {
+    const int64_t t = t0 + lane;
+    bool emit = false;
+    ChildDev ch{};
+    if (t < ncand && accepted[t / (2 * KMAX)]) {
+      const int64_t j = t / (2 * KMAX);
+      const int q = (int)((t >> 1) & (KMAX - 1));
+      const NodeDev v = nodes[j];
+      int k = 0, ls = 0;
+#pragma unroll
+      for (int r = 0; r < KMAX; ++r)
+        if (v.lv[r]) {
+          ++k;
+          ls += v.lv[r];
+        }
+      bool ok = q < k && (level_rule == 1 ? ls + 1 <= max_level + k - 1 : v.lv[q] + 1 <= max_level);
+      if (ok) {
+        ch.comp = v.comp;
+#pragma unroll
+        for (int r = 0; r < KMAX; ++r) {
+          ch.lv[r] = v.lv[r];
+          ch.ix[r] = v.ix[r];
+        }
+        ch.lv[q] = (uint8_t)(ch.lv[q] + 1);
+        ch.ix[q] = (t & 1) ? 2 * ch.ix[q] + 1 : 2 * ch.ix[q] - 1;
+        // rule 0: only the lowest dimension with a parent emits, and every
+        // parent above it must be accepted; rule 1: emit unless a lower
+        // dimension has an accepted parent
+        for (int p = 0; p < k && ok; ++p) {
+          if (p == q || ch.lv[p] <= 1) continue;
+          if (refine_rule == 0 && p < q) {
+            ok = false;
+            break;
+          }
+          if (refine_rule == 1 && p > q) break;
+          uint8_t plv[KMAX];
+          uint32_t pix[KMAX];
+#pragma unroll
+          for (int r = 0; r < KMAX; ++r) {
+            plv[r] = ch.lv[r];
+            pix[r] = ch.ix[r];
+          }
+          plv[p] = (uint8_t)(plv[p] - 1);
+          const uint32_t a = (pix[p] - 1) >> 1, b = (pix[p] + 1) >> 1;
+          pix[p] = (a & 1u) ? a : b;
+          uint32_t lk, sl;
+          node_order(plv, pix, lk, sl);
+          const int64_t pj = find_node(nodes, n, v.comp, lk, sl);
+          const bool pacc = pj >= 0 && accepted[pj];
+          if (refine_rule == 0 ? !pacc : pacc) ok = false;
+        }
+        emit = ok;
+      }
+    }
+    const uint64_t mask = ballot(emit);
+    if (mask) {
+      const int leader = __ffsll((long long)mask) - 1;
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(mask));
+      base = (uint32_t)__shfl((int)base, leader, WAVE);
+      if (emit) out[base + lanes_below(mask)] = ch;
+    }
   }
 }
 
@@ -301,6 +428,10 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
   if (P->refine_rule != 0 && P->refine_rule != 1) return fail(HDMR_EINVAL, "refine_rule must be 0 or 1");
   if (P->form != 0 && P->form != 1) return fail(HDMR_EINVAL, "form must be 0 or 1");
   const bool criteria = P->eps_eta > 0.0 || P->eps_rho > 0.0;
+  // HDMR_REFINE=host admits the children on the host instead of with k_refine
+  // (diagnostics: the grids are the same)
+  const char *refine_env = std::getenv("HDMR_REFINE");
+  const bool host_refine = refine_env && std::strcmp(refine_env, "host") == 0;
   if (!(P->eps_eta == P->eps_eta) || !(P->eps_rho == P->eps_rho)) return fail(HDMR_EINVAL, "eps_eta / eps_rho NaN");
   // ---- index sets requested (all of them, or the candidates of Alg. 2) ----
   std::vector<CompState> all;
@@ -372,6 +503,7 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
       int32_t ls0 = 0;
       for (int q = 0; q < c.k; ++q) ls0 += c.pending[0].l[q];
       if (ls0 != step) continue;
+      if (ls0 - c.k > 31) return fail(HDMR_EUNSUPPORTED, "a grid point's sum of (l_q - 1) exceeds 31");
       for (const NodeKey &key : c.pending) {
         uint32_t lk = 0, sl = 0;
         for (int q = 0; q < c.k; ++q) {
@@ -483,49 +615,60 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
     if (rows_used + N >= (int64_t)INT32_MAX) return fail(HDMR_EUNSUPPORTED, "more than 2^31-1 grid points");
     int rc = grow_device(&D.alpha, &D.alpha_cap, (rows_used + N) * M2, rows_used * M2);
     if (rc) return rc;
-    NodeDev *d_nodes = nullptr;
-    double *d_y = nullptr;
-    int32_t *d_ctoff = nullptr, *d_ctids = nullptr;
-    uint8_t *d_acc = nullptr;
+    // the step's device buffers; what k_refine needs lives to the end of the step
+    struct StepBuffers {
+      NodeDev *nodes = nullptr;
+      double *y = nullptr;
+      int32_t *ctoff = nullptr, *ctids = nullptr;
+      uint8_t *acc = nullptr;
+      ChildDev *kids = nullptr;
+      uint32_t *nkids = nullptr;
+      void free_hier() {
+        (void)hipFree(y);
+        (void)hipFree(ctoff);
+        (void)hipFree(ctids);
+        y = nullptr;
+        ctoff = ctids = nullptr;
+      }
+      ~StepBuffers() {
+        free_hier();
+        (void)hipFree(nodes);
+        (void)hipFree(acc);
+        (void)hipFree(kids);
+        (void)hipFree(nkids);
+      }
+    } SB;
     std::vector<uint8_t> acc((size_t)N);
-    auto cleanup = [&]() {
-      (void)hipFree(d_nodes);
-      (void)hipFree(d_y);
-      (void)hipFree(d_ctoff);
-      (void)hipFree(d_ctids);
-      (void)hipFree(d_acc);
-    };
     hipError_t e = hipSuccess;
-    if ((e = dev_malloc((void **)&d_nodes, sizeof(NodeDev) * N)) != hipSuccess ||
-        (e = dev_malloc((void **)&d_y, sizeof(double) * N * M2)) != hipSuccess ||
-        (e = dev_malloc((void **)&d_ctoff, sizeof(int32_t) * (ncomp + 1))) != hipSuccess ||
-        (e = dev_malloc((void **)&d_ctids, sizeof(int32_t) * std::max<size_t>(ct_ids.size(), 1))) != hipSuccess ||
-        (e = dev_malloc((void **)&d_acc, N)) != hipSuccess ||
-        (e = hipMemcpy(d_nodes, nd.data(), sizeof(NodeDev) * N, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(d_y, yv.data(), sizeof(double) * N * M2, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(d_ctoff, ct_off.data(), sizeof(int32_t) * (ncomp + 1), hipMemcpyHostToDevice)) != hipSuccess ||
+    if ((e = dev_malloc((void **)&SB.nodes, sizeof(NodeDev) * N)) != hipSuccess ||
+        (e = dev_malloc((void **)&SB.y, sizeof(double) * N * M2)) != hipSuccess ||
+        (e = dev_malloc((void **)&SB.ctoff, sizeof(int32_t) * (ncomp + 1))) != hipSuccess ||
+        (e = dev_malloc((void **)&SB.ctids, sizeof(int32_t) * std::max<size_t>(ct_ids.size(), 1))) != hipSuccess ||
+        (e = dev_malloc((void **)&SB.acc, N)) != hipSuccess ||
+        (e = hipMemcpy(SB.nodes, nd.data(), sizeof(NodeDev) * N, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(SB.y, yv.data(), sizeof(double) * N * M2, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(SB.ctoff, ct_off.data(), sizeof(int32_t) * (ncomp + 1), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
         (ct_ids.size() &&
-         (e = hipMemcpy(d_ctids, ct_ids.data(), sizeof(int32_t) * ct_ids.size(), hipMemcpyHostToDevice)) !=
-             hipSuccess)) {
-      cleanup();
+         (e = hipMemcpy(SB.ctids, ct_ids.data(), sizeof(int32_t) * ct_ids.size(), hipMemcpyHostToDevice)) !=
+             hipSuccess))
       return hip_fail(e, "build step upload");
-    }
     {
       dim3 grid((unsigned)std::min<int64_t>((N + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, 65535)), block(256);
       const int opl = (M2 + WAVE - 1) / WAVE;
 #define HIER(OPLV)                                                                                             \
   hipLaunchKernelGGL(k_hierarchize_fp64<OPLV>, grid, block, 0, (hipStream_t)0, D.tups, D.tab, D.alpha, M2, m, \
-                     d_ctoff, d_ctids, d_nodes, N, d_y, P->eps_gamma, d_acc)
+                     SB.ctoff, SB.ctids, SB.nodes, N, SB.y, P->eps_gamma, SB.acc)
       if (opl <= 1) HIER(1);
       else if (opl <= 2) HIER(2);
       else if (opl <= 4) HIER(4);
       else HIER(8);
 #undef HIER
       e = hipGetLastError();
-      if (e == hipSuccess) e = hipMemcpy(acc.data(), d_acc, N, hipMemcpyDeviceToHost);
+      if (e == hipSuccess) e = hipMemcpy(acc.data(), SB.acc, N, hipMemcpyDeviceToHost);
     }
-    cleanup();
     if (e != hipSuccess) return hip_fail(e, "k_hierarchize_fp64");
+    SB.free_hier();
     clk.lap(PhaseClock::HIER);
     // ---- register the new rows; append their level multi-indices ----
     std::vector<int32_t> tab_new;
@@ -580,7 +723,7 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
       h_tups.push_back(T);
       for (int64_t t = t0; t < t1; ++t) {
         const int32_t local = (int32_t)c.acc.size();
-        c.index.emplace(nn[t].key, local);
+        if (host_refine) c.index.emplace(nn[t].key, local);
         c.acc.push_back(acc[t]);
         for (int q = 0; q < c.k; ++q) {
           c.lv.push_back(nn[t].key.l[q]);
@@ -603,58 +746,92 @@ extern "C" int asg_build_components(const asg_build_params *P, hdmr_fn f, void *
     rows_used += N;
     clk.lap(PhaseClock::DIRECTORY);
     // ---- children of accepted nodes (Sec. 3.1 exclusion rule) ----
-    // The nodes are grouped by component (nn is sorted by component) and a
-    // component's nodes stay in one thread, so each pending list is built in
-    // the same order as by one thread.
-    std::vector<int64_t> cstart;
-    for (int64_t j = 0; j < N; ++j)
-      if (j == 0 || nn[j].comp != nn[j - 1].comp) cstart.push_back(j);
-    cstart.push_back(N);
-    parallel_ranges((int64_t)cstart.size() - 1, 8, [&](int64_t g0, int64_t g1) {
-      for (int64_t j = cstart[(size_t)g0]; j < cstart[(size_t)g1]; ++j) {
-        if (!acc[j]) continue;
-        CompState &c = C[nn[j].comp];
-        const NodeKey &key = nn[j].key;
-        int32_t ls = 0;
-        for (int q = 0; q < c.k; ++q) ls += key.l[q];
-        if (P->level_rule == 1 && ls + 1 > P->max_level + c.k - 1) continue;
-        for (int q = 0; q < c.k; ++q) {
-          if (P->level_rule == 0 && key.l[q] + 1 > P->max_level) continue;
-          for (int side = -1; side <= 1; side += 2) {
-            NodeKey ch = key;
-            ch.l[q] = (uint8_t)(ch.l[q] + 1);
-            ch.i[q] = 2 * ch.i[q] + side;
-            int npar = 0, nacc = 0;
-            for (int p = 0; p < c.k; ++p) {
-              if (ch.l[p] <= 1) continue;
-              NodeKey par = ch;
-              par.l[p] = (uint8_t)(par.l[p] - 1);
-              const uint32_t a = (ch.i[p] - 1) / 2, b = (ch.i[p] + 1) / 2;
-              par.i[p] = (a & 1u) ? a : b;
-              ++npar;
-              auto it = c.index.find(par);
-              if (it != c.index.end() && c.acc[it->second]) ++nacc;
-            }
-            const bool admit = P->refine_rule == 0 ? (nacc == npar) : (nacc > 0);
-            if (admit) c.pending.push_back(ch);
+    if (!host_refine) {
+      // k_refine: at most 2 |S| candidates per accepted node, each child once
+      int64_t cap = 0;
+      for (int64_t j = 0; j < N; ++j)
+        if (acc[j]) cap += 2 * C[nn[j].comp].k;
+      if (cap >= (int64_t)INT32_MAX) return fail(HDMR_EUNSUPPORTED, "more than 2^31-1 candidate children in a step");
+      if (cap > 0) {
+        if ((e = dev_malloc((void **)&SB.kids, sizeof(ChildDev) * cap)) != hipSuccess ||
+            (e = dev_malloc((void **)&SB.nkids, sizeof(uint32_t))) != hipSuccess ||
+            (e = hipMemsetAsync(SB.nkids, 0, sizeof(uint32_t), (hipStream_t)0)) != hipSuccess)
+          return hip_fail(e, "refinement buffers");
+        const int64_t ncand = N * 2 * KMAX;
+        hipLaunchKernelGGL(k_refine, dim3((unsigned)std::min<int64_t>((ncand + 255) / 256, 16384)), dim3(256), 0,
+                           (hipStream_t)0, SB.nodes, SB.acc, N, P->max_level, P->level_rule, P->refine_rule, SB.kids,
+                           SB.nkids);
+        uint32_t nk = 0;
+        if ((e = hipGetLastError()) != hipSuccess ||
+            (e = hipMemcpy(&nk, SB.nkids, sizeof(uint32_t), hipMemcpyDeviceToHost)) != hipSuccess)
+          return hip_fail(e, "k_refine");
+        if ((int64_t)nk > cap) return fail(HDMR_EDEVICE, "k_refine returned more children than candidates");
+        std::vector<ChildDev> kids(nk);
+        if (nk && (e = hipMemcpy(kids.data(), SB.kids, sizeof(ChildDev) * nk, hipMemcpyDeviceToHost)) != hipSuccess)
+          return hip_fail(e, "k_refine children");
+        for (const ChildDev &kd : kids) {
+          NodeKey key{};
+          for (int q = 0; q < KMAX; ++q) {
+            key.l[q] = kd.lv[q];
+            key.i[q] = kd.ix[q];
           }
+          C[(size_t)kd.comp].pending.push_back(key);
         }
       }
-    });
-    parallel_ranges((int64_t)C.size(), 8, [&](int64_t s0, int64_t s1) {
-      for (int64_t s = s0; s < s1; ++s) {
-        CompState &c = C[(size_t)s];
-        if (c.pending.size() < 2) continue;
-        std::sort(c.pending.begin(), c.pending.end(), [&](const NodeKey &a, const NodeKey &b) {
-          for (int q = 0; q < c.k; ++q)
-            if (a.l[q] != b.l[q]) return a.l[q] < b.l[q];
-          for (int q = 0; q < c.k; ++q)
-            if (a.i[q] != b.i[q]) return a.i[q] < b.i[q];
-          return false;
-        });
-        c.pending.erase(std::unique(c.pending.begin(), c.pending.end()), c.pending.end());
-      }
-    });
+    } else {
+      // The nodes are grouped by component (nn is sorted by component) and a
+      // component's nodes stay in one thread, so each pending list is built in
+      // the same order as by one thread.
+      std::vector<int64_t> cstart;
+      for (int64_t j = 0; j < N; ++j)
+        if (j == 0 || nn[j].comp != nn[j - 1].comp) cstart.push_back(j);
+      cstart.push_back(N);
+      parallel_ranges((int64_t)cstart.size() - 1, 8, [&](int64_t g0, int64_t g1) {
+        for (int64_t j = cstart[(size_t)g0]; j < cstart[(size_t)g1]; ++j) {
+          if (!acc[j]) continue;
+          CompState &c = C[nn[j].comp];
+          const NodeKey &key = nn[j].key;
+          int32_t ls = 0;
+          for (int q = 0; q < c.k; ++q) ls += key.l[q];
+          if (P->level_rule == 1 && ls + 1 > P->max_level + c.k - 1) continue;
+          for (int q = 0; q < c.k; ++q) {
+            if (P->level_rule == 0 && key.l[q] + 1 > P->max_level) continue;
+            for (int side = -1; side <= 1; side += 2) {
+              NodeKey ch = key;
+              ch.l[q] = (uint8_t)(ch.l[q] + 1);
+              ch.i[q] = 2 * ch.i[q] + side;
+              int npar = 0, nacc = 0;
+              for (int p = 0; p < c.k; ++p) {
+                if (ch.l[p] <= 1) continue;
+                NodeKey par = ch;
+                par.l[p] = (uint8_t)(par.l[p] - 1);
+                const uint32_t a = (ch.i[p] - 1) / 2, b = (ch.i[p] + 1) / 2;
+                par.i[p] = (a & 1u) ? a : b;
+                ++npar;
+                auto it = c.index.find(par);
+                if (it != c.index.end() && c.acc[it->second]) ++nacc;
+              }
+              const bool admit = P->refine_rule == 0 ? (nacc == npar) : (nacc > 0);
+              if (admit) c.pending.push_back(ch);
+            }
+          }
+        }
+      });
+      parallel_ranges((int64_t)C.size(), 8, [&](int64_t s0, int64_t s1) {
+        for (int64_t s = s0; s < s1; ++s) {
+          CompState &c = C[(size_t)s];
+          if (c.pending.size() < 2) continue;
+          std::sort(c.pending.begin(), c.pending.end(), [&](const NodeKey &a, const NodeKey &b) {
+            for (int q = 0; q < c.k; ++q)
+              if (a.l[q] != b.l[q]) return a.l[q] < b.l[q];
+            for (int q = 0; q < c.k; ++q)
+              if (a.i[q] != b.i[q]) return a.i[q] < b.i[q];
+            return false;
+          });
+          c.pending.erase(std::unique(c.pending.begin(), c.pending.end()), c.pending.end());
+        }
+      });
+    }
     clk.lap(PhaseClock::CHILDREN);
   }
   return HDMR_OK;

@@ -65,6 +65,65 @@ def test_adaptive_build_matches_oracle(hd, refine_rule):
     _compare_models(hd, gm, model)
 
 
+def _export_all(hd, gm):
+    info = hd.hdmr_get_info(gm)
+    out = []
+    for s in range(info["n_components"]):
+        dims, lv, ix, al, w = hd.hdmr_export_component(gm, s)
+        out.append((dims, np.asarray(lv).copy(), np.asarray(ix).copy(),
+                    np.ascontiguousarray(al).view(np.uint64).copy(), w))
+    return info, out
+
+
+_REFINE_CASES = {
+    # (d, m, pairs, comps or max_order, build keywords)
+    "rule0": (8, 5, "c2", None, dict(max_level=8, eps_gamma=1e-4, refine_rule=0)),
+    "rule1": (8, 5, "c2", None, dict(max_level=8, eps_gamma=1e-4, refine_rule=1)),
+    "order3_level_rule0": (5, 3, [(0, 1), (1, 2), (2, 3), (3, 4)], 3, dict(max_level=5, level_rule=0, eps_gamma=1e-5)),
+    "order3_level_rule1": (5, 3, [(0, 1), (1, 2), (2, 3), (3, 4)], 3, dict(max_level=7, level_rule=1, eps_gamma=1e-5)),
+    "order4_regular": (4, 2, [(0, 1), (2, 3)], 4, dict(max_level=4, level_rule=1, eps_gamma=-1.0)),
+    "alg2_criteria": (6, 4, [(0, 1), (2, 3), (1, 4)], 3, dict(max_level=6, eps_gamma=1e-4, eps_eta=1e-9)),
+    "nothing_accepted": (6, 4, [(0, 1)], 2, dict(max_level=6, eps_gamma=1e9)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(_REFINE_CASES))
+def test_device_refinement_matches_host(hd, monkeypatch, case):
+    """k_refine (the default) against the host's admission of children
+    (HDMR_REFINE=host): the same grid rows in the same order and bitwise the
+    same surpluses, since each step's node order depends only on the set of
+    admitted children."""
+    d, m, pairs, order, kw = _REFINE_CASES[case]
+    if pairs == "c2":
+        cfg = ws.config("c2", d=d, m=m, npairs="all", max_level=kw["max_level"])
+        tf, anchor = ws.test_function_for(cfg), cfg["anchor"]
+        args = dict(comps=cfg["comps"])
+    else:
+        tf = ws.TestFunction(d, m, pairs, seed=23)
+        anchor = tf.ref
+        args = dict(max_order=order)
+    gms = {}
+    for mode in ("host", "device"):
+        if mode == "host":
+            monkeypatch.setenv("HDMR_REFINE", "host")
+        else:
+            monkeypatch.delenv("HDMR_REFINE", raising=False)
+        gms[mode] = hd.asg_build_components(d, m, anchor, (tf.c_fn, tf.c_user), **args, **kw)
+    ih, ch = _export_all(hd, gms["host"])
+    idv, cd = _export_all(hd, gms["device"])
+    assert ih == idv
+    assert len(ch) == len(cd)
+    for (dh, lh, xh, ah, wh), (dd, ld, xd, ad, wd) in zip(ch, cd):
+        assert dh == dd and wh == wd
+        np.testing.assert_array_equal(lh, ld)
+        np.testing.assert_array_equal(xh, xd)
+        np.testing.assert_array_equal(ah, ad)
+    if "eps_eta" in kw:
+        rh, rd = hd.hdmr_build_report(gms["host"]), hd.hdmr_build_report(gms["device"])
+        assert rh["candidates"] == rd["candidates"] and list(rh["kept"]) == list(rd["kept"])
+    print("%s: %d rows in %d components, identical" % (case, ih["n_rows"], ih["n_components"]))
+
+
 @pytest.mark.parametrize("level_rule", [0, 1])
 def test_regular_limit_and_three_dim_components(hd, level_rule):
     d, m = 4, 3
